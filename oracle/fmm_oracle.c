@@ -21,8 +21,9 @@
  *    bisections (Section 2.1.2, eta = 1), each along the longest edge of the
  *    current cell (ties: x before y before z).  The low side receives
  *    floor(n/2) points in the total order (coordinate, original index), the
- *    split plane is the midpoint of the two middle coordinates (cell midpoint
- *    when n < 2), and the partition is stable (points keep ascending original
+ *    split plane is the midpoint of the two middle coordinates (the point's
+ *    own coordinate when n = 1, the cell midpoint when n = 0), and the
+ *    partition is stable (points keep ascending original
  *    index inside every box).  Child number = 4*b1 + 2*b2 + b3 with b_i = 1
  *    for the high side of bisection i; global index 8*parent + child.
  *    Coordinates are read through x + 0.0, which maps -0.0 to +0.0.
@@ -409,9 +410,12 @@ static int64_t bisect(const orc_tree* t, int32_t* perm, int64_t s, int64_t e, co
   const int64_t n = e - s;
   const int64_t m = n / 2;
   double plane;
-  if (n < 2) {
+  if (n == 0) {
     plane = 0.5 * (lo[axis] + hi[axis]);
-    /* n == 1: the single point goes to the high side (low side gets 0) */
+  } else if (n == 1) {
+    /* the single point goes to the high side (the low side gets floor(1/2) = 0
+     * points) and the plane passes through it, so it stays inside its cell */
+    plane = coord(t, axis, perm[s]);
   } else {
     for (int64_t i = 0; i < n; ++i) { kv[i].key = coord(t, axis, perm[s + i]); kv[i].idx = perm[s + i]; }
     qsort(kv, (size_t)n, sizeof(kv_t), kv_cmp);

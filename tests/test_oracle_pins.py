@@ -150,6 +150,19 @@ def test_tree_invariants(orc, gen):
             assert np.all(g[b, 0:3] >= gp[b // 8, 0:3]) and np.all(g[b, 3:6] <= gp[b // 8, 3:6])
 
 
+@pytest.mark.parametrize("n,levels", [(5, 2), (30, 2), (9, 1), (100, 3)])
+def test_tree_sparse_points_inside_cells(orc, n, levels):
+    """With fewer points than leaves some bisections see one point; every
+    point must still lie in the closed cell of its leaf."""
+    x, y, z, _ = W.gaussian_mixture(n, seed=n)
+    t = orc.Tree(x, y, z, levels, 0.5)
+    perm, s, g = t.perm(), t.start(levels), t.geom(levels)
+    P = np.stack([x, y, z], axis=1)
+    for b in range(8 ** levels):
+        idx = perm[s[b]:s[b + 1]]
+        assert np.all(P[idx] >= g[b, 0:3]) and np.all(P[idx] <= g[b, 3:6])
+
+
 def test_tree_power_of_two_scaling(orc):
     x, y, z, _ = W.gaussian_mixture(3000, seed=9)
     a = orc.Tree(x, y, z, 2, 0.5)
