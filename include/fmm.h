@@ -1,0 +1,158 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) balanced-tree fast multipole library
+ * for the 3D harmonic kernel.
+ *
+ * The library evaluates, for N source points x_i with charges q_i,
+ *     phi_i = sum_{j != i} q_j / |x_i - x_j|           (Section 2, eq. (2.1))
+ *     E_i   = -grad phi_i = sum_{j != i} q_j (x_i - x_j) / |x_i - x_j|^3
+ * with the balanced-tree FMM of Bull & Engblom (Section 2): a tree of L
+ * levels of 8-way median splits (Section 2.1.2, eta = 1), theta-criterion
+ * connectivity (Section 2.1.1, eq. (2.2)), P2M/M2M upward (Algorithm 1),
+ * M2L/L2L downward (Algorithm 3) and L2P/P2P evaluation (Algorithm 4).
+ * Pairs of points at distance zero contribute nothing.
+ *
+ * Conventions shared by every entry point:
+ *  - Point data are structure-of-arrays, IEEE binary64, in the caller's order.
+ *  - Arrays named "device" are HIP device pointers that must stay valid until
+ *    the work enqueued on `stream` has completed; the library never frees
+ *    caller memory.  Arrays named "host" are ordinary host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *  - Every function returns FMM_OK (0) or a negative status; on failure no
+ *    output is defined, nothing leaks, and fmm_last_error() returns a message
+ *    (per calling thread).  Argument checks happen before any work is
+ *    enqueued.  No exception crosses the ABI.
+ *  - A tree handle may be used by one thread at a time.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_tree fmm_tree;
+
+enum fmm_status {
+  FMM_OK = 0,
+  FMM_EINVAL = -1,       /* invalid argument (NULL pointer, range, non-finite coordinate) */
+  FMM_ENOMEM = -2,       /* device or host allocation failed */
+  FMM_EDEVICE = -3,      /* HIP runtime error (no device, launch failure, ...) */
+  FMM_EUNSUPPORTED = -4  /* valid request this build does not support */
+};
+
+#define FMM_MAX_LEVELS 8
+#define FMM_MAX_ORDER 20
+#define FMM_MAX_POINTS 2147483647LL
+
+/* Result selection for fmm_evaluate_tree_parts (Algorithm 4 splits the
+ * evaluation into the far field, L2P, and the near field, P2P). */
+#define FMM_PART_NEAR 1
+#define FMM_PART_FAR 2
+#define FMM_PART_ALL 3
+
+/*
+ * Builds the tree (Section 2.1.2 and Algorithm 2 on one process).
+ *   x, y, z  device, n doubles each: point coordinates (finite, |coord| <= 1e300).
+ *   n        1 <= n <= FMM_MAX_POINTS.
+ *   levels   0 <= levels <= FMM_MAX_LEVELS; the tree has 8^levels leaves.
+ *   theta    0 <= theta < 1, the parameter of eq. (2.2).
+ *   out      host: receives a new handle that owns all device workspace.
+ * The coordinates are read during the call only (the handle keeps a copy in
+ * tree order).  The call synchronises `stream` once per level (interaction
+ * list sizes are read back to size the lists).  Non-finite coordinates give
+ * FMM_EINVAL.
+ */
+int fmm_build(const double* x, const double* y, const double* z, int64_t n, int levels, double theta,
+              void* stream, fmm_tree** out);
+
+/*
+ * Evaluates potential and field for charges q on a built tree (Algorithm 1:
+ * P2M, M2M, then Algorithm 3 and Algorithm 4).
+ *   q                      device, n doubles, caller's point order.
+ *   p                      0 <= p <= FMM_MAX_ORDER: expansions keep degrees 0..p.
+ *   pot, ex, ey, ez        device, n doubles each, written in the caller's order.
+ * Fully asynchronous on `stream`; may be called many times on one tree.
+ */
+int fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, double* ex, double* ey, double* ez,
+                      void* stream);
+
+/* As fmm_evaluate_tree, but writes only the near-field (P2P) part, the
+ * far-field (L2P) part, or both (FMM_PART_*): used to check each half of
+ * Algorithm 4 separately. */
+int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
+                            double* ez, void* stream);
+
+/* One-shot form: fmm_build + fmm_evaluate_tree + fmm_free.  All arrays are
+ * device arrays of n doubles. */
+int fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,
+                 int levels, double* pot, double* ex, double* ey, double* ez, void* stream);
+
+/* Releases a handle and its device memory (stream-ordered on the stream of the
+ * last call that used it).  NULL is accepted. */
+int fmm_free(fmm_tree* tree);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* fmm_last_error(void);
+
+/* ---- Introspection (used by parity tests; synchronous, host outputs) ---- */
+
+/* n, levels and theta of a tree (any output pointer may be NULL). */
+int fmm_tree_info(const fmm_tree* tree, int64_t* n, int* levels, double* theta);
+
+/* host perm[n]: original index of the point at each tree position.  Points
+ * of every leaf occupy a contiguous range in ascending original index. */
+int fmm_tree_perm(const fmm_tree* tree, int32_t* perm);
+
+/* host geom[8^level * 10]: per box lo[3], hi[3], centre[3], radius (cell
+ * centre and half-diagonal, Section 2.1.1), and host start[8^level + 1]:
+ * point range of each box in tree order (either pointer may be NULL). */
+int fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start);
+
+/* Connectivity of one level (Section 2.2.1: per-level sparse connectivity),
+ * as CSR by target box, ascending source box index within each row.
+ *   kind 0 = strongly connected (incl. the box itself), 1 = weakly connected.
+ *   nnz      host, receives the number of entries.
+ *   offsets  host, 8^level + 1 entries, or NULL.
+ *   idx      host, nnz entries (box indices of that level), or NULL. */
+int fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int64_t* offsets, int32_t* idx);
+
+/* Work counts of a tree: M2L translations (weak pairs over all levels) and
+ * P2P interactions (ordered point pairs in strongly connected leaves, minus
+ * the n self pairs). */
+int fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs);
+
+/* ---- Phase timing ------------------------------------------------------ */
+
+/* Phases timed with HIP events on the call's stream when profiling is on. */
+enum fmm_phase {
+  FMM_PH_TREE = 0,  /* bounding box, median bisections, box geometry */
+  FMM_PH_LISTS,     /* theta-criterion lists */
+  FMM_PH_P2M,
+  FMM_PH_M2M,
+  FMM_PH_M2L,
+  FMM_PH_L2L,
+  FMM_PH_L2P,
+  FMM_PH_P2P,       /* near field, combined with L2P and scattered to the caller's order */
+  FMM_NUM_PHASES
+};
+
+/* Turns event timing on (1) or off (0) for subsequent calls on this thread. */
+int fmm_set_profiling(int on);
+
+/* host ms[FMM_NUM_PHASES]: durations of the phases of the most recent
+ * fmm_build / fmm_evaluate_tree on this thread (0 for phases not run).
+ * Waits for those events. */
+int fmm_last_timings(double* ms);
+
+/* Upper estimate of the device bytes a build + evaluation needs (weak-list
+ * sizes estimated for a uniform cloud), for admission control. */
+size_t fmm_bytes_estimate(int64_t n, int levels, double theta, int p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H */

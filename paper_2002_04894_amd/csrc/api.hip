@@ -1,0 +1,370 @@
+// C ABI of the library (declared in include/fmm.h): argument validation,
+// error reporting, stream-ordered allocation, phase timing and the
+// introspection exports.  No exception crosses this layer.
+#include <math.h>
+#include <string.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+
+#include "fmm_internal.h"
+
+struct fmm_tree {
+  fmm::Tree t;
+};
+
+namespace fmm {
+
+namespace {
+thread_local std::string g_err;
+
+void set_err(const std::string& m) { g_err = m; }
+
+std::once_flag g_pool_once;
+void init_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return FMM_OK;
+  } catch (const Error& e) {
+    set_err(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_err("host allocation failed");
+    return FMM_ENOMEM;
+  } catch (...) {
+    set_err("unexpected internal error");
+    return FMM_EDEVICE;
+  }
+}
+
+void release(Tree& t) {
+  hipStream_t s = t.stream;
+  auto f = [&](void* p) {
+    if (p) (void)hipFreeAsync(p, s);
+  };
+  f(t.px);
+  f(t.py);
+  f(t.pz);
+  f(t.perm);
+  for (Level& V : t.lev) {
+    f(V.geom);
+    f(V.start);
+    f(V.s_off);
+    f(V.s_idx);
+    f(V.w_off);
+    f(V.w_idx);
+  }
+  t.lev.clear();
+  t.px = t.py = t.pz = nullptr;
+  t.perm = nullptr;
+}
+
+// ---- phase timer ----
+struct TimerState {
+  bool on = false;
+  hipEvent_t ev[FMM_NUM_PHASES][2] = {};
+  bool used[FMM_NUM_PHASES] = {};
+  bool created = false;
+};
+thread_local TimerState g_tm;
+
+}  // namespace
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? FMM_ENOMEM : FMM_EDEVICE;
+  fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* dalloc(size_t bytes, hipStream_t s) {
+  std::call_once(g_pool_once, init_pool);
+  void* p = nullptr;
+  const hipError_t e = hipMallocAsync(&p, bytes ? bytes : 8, s);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    fail(FMM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+void dfree(void* p, hipStream_t s) {
+  if (p) HIPCHECK(hipFreeAsync(p, s));
+}
+
+LevelView Tree::view() const {
+  LevelView v{};
+  v.L = L;
+  for (int l = 0; l <= L; ++l) {
+    const Level& V = lev[l];
+    v.gofs[l] = V.gofs;
+    v.geom[l] = V.geom;
+    v.start[l] = V.start;
+    v.s_off[l] = V.s_off;
+    v.s_idx[l] = V.s_idx;
+    v.w_off[l] = V.w_off;
+    v.w_idx[l] = V.w_idx;
+  }
+  v.gofs[L + 1] = nbox_total;
+  return v;
+}
+
+PhaseTimer& timer() {
+  static thread_local PhaseTimer t;
+  return t;
+}
+
+void PhaseTimer::reset() {
+  for (bool& u : g_tm.used) u = false;
+}
+
+void PhaseTimer::begin(int ph, hipStream_t s) {
+  if (!g_tm.on) return;
+  if (!g_tm.created) {
+    for (auto& e : g_tm.ev) {
+      HIPCHECK(hipEventCreate(&e[0]));
+      HIPCHECK(hipEventCreate(&e[1]));
+    }
+    g_tm.created = true;
+  }
+  HIPCHECK(hipEventRecord(g_tm.ev[ph][0], s));
+  g_tm.used[ph] = true;
+}
+
+void PhaseTimer::end(int ph, hipStream_t s) {
+  if (!g_tm.on) return;
+  HIPCHECK(hipEventRecord(g_tm.ev[ph][1], s));
+}
+
+}  // namespace fmm
+
+using fmm::Error;
+using fmm::fail;
+
+namespace {
+
+void validate_points(const void* x, const void* y, const void* z, int64_t n) {
+  if (!x || !y || !z) fail(FMM_EINVAL, "coordinate pointer is NULL");
+  if (n < 1 || n > FMM_MAX_POINTS) fail(FMM_EINVAL, "n must be in [1, 2^31-1]");
+}
+
+void validate_tree_args(int levels, double theta) {
+  if (levels < 0 || levels > FMM_MAX_LEVELS) fail(FMM_EINVAL, "levels must be in [0, 8]");
+  if (!(theta >= 0.0 && theta < 1.0)) fail(FMM_EINVAL, "theta must be in [0, 1)");
+}
+
+void validate_eval_args(const void* q, int p, const void* a, const void* b, const void* c, const void* d) {
+  if (!q) fail(FMM_EINVAL, "charge pointer is NULL");
+  if (!a || !b || !c || !d) fail(FMM_EINVAL, "output pointer is NULL");
+  if (p < 0 || p > FMM_MAX_ORDER) fail(FMM_EINVAL, "p must be in [0, 20]");
+}
+
+void ensure_device() {
+  int cnt = 0;
+  const hipError_t e = hipGetDeviceCount(&cnt);
+  if (e != hipSuccess || cnt < 1) {
+    (void)hipGetLastError();
+    fail(FMM_EDEVICE, "no HIP device available");
+  }
+}
+
+fmm_tree* build_impl(const double* x, const double* y, const double* z, int64_t n, int levels, double theta,
+                     hipStream_t s) {
+  validate_points(x, y, z, n);
+  validate_tree_args(levels, theta);
+  ensure_device();
+  fmm_tree* h = new fmm_tree();
+  fmm::Tree& t = h->t;
+  t.n = n;
+  t.L = levels;
+  t.theta = theta;
+  t.stream = s;
+  t.p2p_pairs = -1;
+  try {
+    fmm::timer().reset();
+    fmm::timer().begin(FMM_PH_TREE, s);
+    fmm::tree_build(t, x, y, z, s);
+    fmm::timer().end(FMM_PH_TREE, s);
+    fmm::timer().begin(FMM_PH_LISTS, s);
+    fmm::lists_build(t, s);
+    fmm::timer().end(FMM_PH_LISTS, s);
+  } catch (...) {
+    fmm::release(t);
+    delete h;
+    throw;
+  }
+  return h;
+}
+
+const fmm::Tree& get(const fmm_tree* h) {
+  if (!h) fail(FMM_EINVAL, "tree handle is NULL");
+  return h->t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmm_build(const double* x, const double* y, const double* z, int64_t n, int levels, double theta, void* stream,
+              fmm_tree** out) {
+  return fmm::guarded([&] {
+    if (!out) fail(FMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    *out = build_impl(x, y, z, n, levels, theta, (hipStream_t)stream);
+  });
+}
+
+int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
+                            double* ez, void* stream) {
+  return fmm::guarded([&] {
+    fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
+    validate_eval_args(q, p, pot, ex, ey, ez);
+    if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
+    t.stream = (hipStream_t)stream;
+    fmm::evaluate(t, q, p, parts, pot, ex, ey, ez, (hipStream_t)stream);
+  });
+}
+
+int fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, double* ex, double* ey, double* ez,
+                      void* stream) {
+  return fmm_evaluate_tree_parts(tree, q, p, FMM_PART_ALL, pot, ex, ey, ez, stream);
+}
+
+int fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,
+                 int levels, double* pot, double* ex, double* ey, double* ez, void* stream) {
+  return fmm::guarded([&] {
+    validate_points(x, y, z, n);
+    validate_tree_args(levels, theta);
+    validate_eval_args(q, p, pot, ex, ey, ez);
+    hipStream_t s = (hipStream_t)stream;
+    fmm_tree* h = build_impl(x, y, z, n, levels, theta, s);
+    try {
+      fmm::evaluate(h->t, q, p, FMM_PART_ALL, pot, ex, ey, ez, s);
+    } catch (...) {
+      fmm::release(h->t);
+      delete h;
+      throw;
+    }
+    fmm::release(h->t);
+    delete h;
+  });
+}
+
+int fmm_free(fmm_tree* tree) {
+  return fmm::guarded([&] {
+    if (!tree) return;
+    fmm::release(tree->t);
+    delete tree;
+  });
+}
+
+const char* fmm_last_error(void) { return fmm::g_err.c_str(); }
+
+int fmm_tree_info(const fmm_tree* tree, int64_t* n, int* levels, double* theta) {
+  return fmm::guarded([&] {
+    const fmm::Tree& t = get(tree);
+    if (n) *n = t.n;
+    if (levels) *levels = t.L;
+    if (theta) *theta = t.theta;
+  });
+}
+
+int fmm_tree_perm(const fmm_tree* tree, int32_t* perm) {
+  return fmm::guarded([&] {
+    const fmm::Tree& t = get(tree);
+    if (!perm) fail(FMM_EINVAL, "perm is NULL");
+    HIPCHECK(hipStreamSynchronize(t.stream));
+    HIPCHECK(hipMemcpy(perm, t.perm, t.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+  });
+}
+
+int fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start) {
+  return fmm::guarded([&] {
+    const fmm::Tree& t = get(tree);
+    if (level < 0 || level > t.L) fail(FMM_EINVAL, "level out of range");
+    const fmm::Level& V = t.lev[level];
+    HIPCHECK(hipStreamSynchronize(t.stream));
+    if (geom) HIPCHECK(hipMemcpy(geom, V.geom, V.nbox * 10 * sizeof(double), hipMemcpyDeviceToHost));
+    if (start) {
+      std::vector<int32_t> tmp(V.nbox + 1);
+      HIPCHECK(hipMemcpy(tmp.data(), V.start, (V.nbox + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i <= V.nbox; ++i) start[i] = tmp[i];
+    }
+  });
+}
+
+int fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int64_t* offsets, int32_t* idx) {
+  return fmm::guarded([&] {
+    const fmm::Tree& t = get(tree);
+    if (level < 0 || level > t.L) fail(FMM_EINVAL, "level out of range");
+    if (kind != 0 && kind != 1) fail(FMM_EINVAL, "kind must be 0 (strong) or 1 (weak)");
+    const fmm::Level& V = t.lev[level];
+    const int64_t cnt = kind == 0 ? V.s_nnz : V.w_nnz;
+    if (nnz) *nnz = cnt;
+    HIPCHECK(hipStreamSynchronize(t.stream));
+    if (offsets)
+      HIPCHECK(hipMemcpy(offsets, kind == 0 ? V.s_off : V.w_off, (V.nbox + 1) * sizeof(int64_t),
+                         hipMemcpyDeviceToHost));
+    if (idx && cnt > 0)
+      HIPCHECK(hipMemcpy(idx, kind == 0 ? V.s_idx : V.w_idx, cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+  });
+}
+
+int fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs) {
+  return fmm::guarded([&] {
+    fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
+    if (t.p2p_pairs < 0) fmm::tree_compute_stats(t, t.stream);
+    if (m2l_pairs) *m2l_pairs = t.m2l_pairs;
+    if (p2p_pairs) *p2p_pairs = t.p2p_pairs;
+  });
+}
+
+int fmm_set_profiling(int on) {
+  fmm::g_tm.on = on != 0;
+  return FMM_OK;
+}
+
+int fmm_last_timings(double* ms) {
+  return fmm::guarded([&] {
+    if (!ms) fail(FMM_EINVAL, "ms is NULL");
+    for (int k = 0; k < FMM_NUM_PHASES; ++k) {
+      ms[k] = 0.0;
+      if (!fmm::g_tm.on || !fmm::g_tm.created || !fmm::g_tm.used[k]) continue;
+      HIPCHECK(hipEventSynchronize(fmm::g_tm.ev[k][1]));
+      float v = 0.f;
+      HIPCHECK(hipEventElapsedTime(&v, fmm::g_tm.ev[k][0], fmm::g_tm.ev[k][1]));
+      ms[k] = v;
+    }
+  });
+}
+
+size_t fmm_bytes_estimate(int64_t n, int levels, double theta, int p) {
+  if (n < 1 || levels < 0 || levels > FMM_MAX_LEVELS || p < 0 || p > FMM_MAX_ORDER) return 0;
+  if (!(theta >= 0.0 && theta < 1.0)) return 0;
+  int64_t nbox = 0;
+  for (int l = 0; l <= levels; ++l) nbox += (int64_t)1 << (3 * l);
+  const double th = theta > 0.05 ? theta : 0.05;
+  // weak and strong links per box on a uniform lattice grow like theta^-3
+  const double links = 650.0 * (0.125 / (th * th * th)) + 100.0;
+  const size_t pts = (size_t)n * (2 * 28 + 8 + 4 * 8 + 8);
+  const size_t geo = (size_t)nbox * (10 * 8 + 4 + 16) + ((size_t)2 << (3 * levels)) * (6 * 8 + 8);
+  const size_t lists = (size_t)((double)nbox * links * 4.0);
+  const size_t expn = (size_t)nbox * (size_t)(p + 1) * (p + 1) * 8 * 2;
+  return pts + geo + lists + expn + ((size_t)64 << 20);
+}
+
+}  // extern "C"

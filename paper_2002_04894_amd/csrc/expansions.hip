@@ -1,0 +1,644 @@
+// Multipole / local expansions on the GPU (Section 2.1: spherical-harmonic
+// expansions of order p about box centres; Algorithm 1 P2M and M2M,
+// Algorithm 3 M2L and L2L, Algorithm 4 L2P).
+//
+// Basis.  Real regular solid harmonics R_b(u) = |u|^n Y_b(u/|u|), where Y_b
+// are the Schmidt semi-normalised real harmonics of degree n (b runs over
+// c_0, c_1, s_1, ..., c_n, s_n; storage index n^2, n^2 + 2m - 1, n^2 + 2m).
+// Within one degree they are orthogonal with equal norms, so a rotation acts
+// on the 2n+1 coefficients of degree n by an orthogonal matrix, and
+//   1/|x - y| = sum_b R_b(y) I_b(x),  I_b(x) = R_b(x) / |x|^(2n+1),  |y| < |x|.
+// Hence the multipole M_b = sum_i q_i R_b(x_i - c) and the local expansion
+// Phi(x) = sum_b L_b R_b(x - c).  With G_n^m = sqrt((n-m)!/(n+m)!) r^n P_n^m
+// e^{i m phi} (no Condon-Shortley phase), R_{n,m,c} + i R_{n,m,s} =
+// sqrt(2 - delta_m0) G_n^m, and G obeys
+//   G_m^m     = sqrt((2m-1)/(2m)) (x + i y) G_{m-1}^{m-1},
+//   G_{m+1}^m = sqrt(2m+1) z G_m^m,
+//   G_n^m     = [(2n-1) z G_{n-1}^m - sqrt((n+m-1)(n-m-1)) r^2 G_{n-2}^m] / sqrt((n+m)(n-m)).
+//
+// Translations use the rotational form the paper adopts for M2L (Section
+// 2.1.3): rotate the expansion so that the translation vector is the +z axis,
+// translate along z, rotate back; O(p^3) per translation.  A rotation
+// Ry(g) equals J Rz(g) J^T with J the fixed matrix of a quarter turn about x
+// (tabulated per degree by exact quadrature), and z-rotations mix the
+// (c_m, s_m) pairs, so no per-pair rotation matrix is generated.  Along z the
+// translations are, with rho the distance:
+//   M2L:  L'_{j,m} = sum_n (-1)^(n+m) (n+j)! / (rho^(n+j+1) sqrt((n+m)!(n-m)!(j+m)!(j-m)!)) M'_{n,m}
+//   M2M:  M'_{n,m} = sum_{j<=n} rho^(n-j)/(n-j)! sqrt((n+m)!(n-m)!/((j+m)!(j-m)!)) M_{j,m}
+//   L2L:  L'_{j,m} = sum_{n>=j} (same coefficient) L_{n,m}
+// (identical for the c and s parts of each m).
+#include <math.h>
+
+#include <map>
+#include <mutex>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+// ----------------------------------------------------------------------------
+// host: fixed tables
+// ----------------------------------------------------------------------------
+namespace {
+
+// real regular solid harmonics at v, degrees <= p (host, for the quadrature)
+void host_R(int p, const double v[3], double* out) {
+  const double x = v[0], y = v[1], z = v[2];
+  const double r2 = x * x + y * y + z * z;
+  std::vector<double> gr((p + 1) * (p + 1)), gi((p + 1) * (p + 1));
+  auto at = [&](int n, int m) { return n * (p + 1) + m; };
+  gr[at(0, 0)] = 1.0;
+  gi[at(0, 0)] = 0.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      const double a = sqrt((2.0 * m - 1.0) / (2.0 * m));
+      const double pr = gr[at(m - 1, m - 1)], pi = gi[at(m - 1, m - 1)];
+      gr[at(m, m)] = a * (x * pr - y * pi);
+      gi[at(m, m)] = a * (x * pi + y * pr);
+    }
+    if (m + 1 <= p) {
+      const double b = sqrt(2.0 * m + 1.0);
+      gr[at(m + 1, m)] = b * z * gr[at(m, m)];
+      gi[at(m + 1, m)] = b * z * gi[at(m, m)];
+    }
+    for (int n = m + 2; n <= p; ++n) {
+      const double d = sqrt((double)(n + m) * (n - m));
+      const double c1 = (2.0 * n - 1.0) / d;
+      const double c2 = sqrt((double)(n + m - 1) * (n - m - 1)) / d;
+      gr[at(n, m)] = c1 * z * gr[at(n - 1, m)] - c2 * r2 * gr[at(n - 2, m)];
+      gi[at(n, m)] = c1 * z * gi[at(n - 1, m)] - c2 * r2 * gi[at(n - 2, m)];
+    }
+  }
+  const double s2 = sqrt(2.0);
+  for (int n = 0; n <= p; ++n) {
+    out[n * n] = gr[at(n, 0)];
+    for (int m = 1; m <= n; ++m) {
+      out[n * n + 2 * m - 1] = s2 * gr[at(n, m)];
+      out[n * n + 2 * m] = s2 * gi[at(n, m)];
+    }
+  }
+}
+
+// Gauss-Legendre nodes / weights on [-1, 1] by Newton iteration
+void gauss_legendre(int N, std::vector<double>& xs, std::vector<double>& ws) {
+  xs.resize(N);
+  ws.resize(N);
+  for (int i = 0; i < N; ++i) {
+    double x = cos(M_PI * (i + 0.75) / (N + 0.5));
+    double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= N; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_N(x), p0 = P_{N-1}(x)
+      dp = N * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    xs[i] = x;
+    ws[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+// x-parity class of local index i within a degree: c_m (i = 2m-1) and s_m
+// (i = 2m) are even under x -> -x iff m + [s] is even.
+int parity_class(int i) {
+  if (i == 0) return 0;
+  const int m = (i + 1) >> 1, s = (i & 1) ? 0 : 1;
+  return (m + s) & 1;
+}
+
+struct HostTables {
+  std::vector<double> J, A, B, rc;
+  std::vector<int> joff;
+};
+
+HostTables make_host_tables(int p) {
+  HostTables h;
+  // J: R_b(K v) = sum_b' J_bb' R_b'(v), K = quarter turn about x: (x,y,z) -> (x, z, -y)
+  h.joff.resize(p + 2);
+  h.joff[0] = 0;
+  for (int n = 0; n <= p; ++n) h.joff[n + 1] = h.joff[n] + (2 * n + 1) * (2 * n + 1);
+  h.J.assign(h.joff[p + 1], 0.0);
+  const int nth = p + 2, nph = 2 * p + 2;
+  std::vector<double> gx, gw;
+  gauss_legendre(nth, gx, gw);
+  const int nt = nterms(p);
+  std::vector<double> Rv(nt), RK(nt);
+  std::vector<long double> acc(h.joff[p + 1], 0.0L);
+  for (int a = 0; a < nth; ++a) {
+    const double ct = gx[a];
+    const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    for (int k = 0; k < nph; ++k) {
+      const double ph = 2.0 * M_PI * k / nph;
+      const double v[3] = {st * cos(ph), st * sin(ph), ct};
+      const double kv[3] = {v[0], v[2], -v[1]};
+      host_R(p, v, Rv.data());
+      host_R(p, kv, RK.data());
+      const long double w = (long double)gw[a] * (2.0L * M_PI / nph);
+      for (int n = 0; n <= p; ++n) {
+        const int s = 2 * n + 1;
+        for (int i = 0; i < s; ++i)
+          for (int j = 0; j < s; ++j)
+            acc[h.joff[n] + i * s + j] += w * (long double)RK[n * n + i] * (long double)Rv[n * n + j];
+      }
+    }
+  }
+  for (int n = 0; n <= p; ++n) {
+    const int s = 2 * n + 1;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) {
+        const long double v = acc[h.joff[n] + i * s + j] * (2.0L * n + 1.0L) / (4.0L * M_PI);
+        h.J[h.joff[n] + i * s + j] = parity_class(i) == parity_class(j) ? (double)v : 0.0;
+      }
+  }
+  // factorials
+  std::vector<long double> f(2 * p + 2);
+  f[0] = 1.0L;
+  for (int i = 1; i < (int)f.size(); ++i) f[i] = f[i - 1] * i;
+  const int P1 = p + 1;
+  h.A.assign((size_t)P1 * P1 * P1, 0.0);
+  h.B.assign((size_t)P1 * P1 * P1, 0.0);
+  for (int m = 0; m <= p; ++m)
+    for (int j = m; j <= p; ++j)
+      for (int n = m; n <= p; ++n) {
+        const long double sgn = ((n + m) & 1) ? -1.0L : 1.0L;
+        h.A[((size_t)m * P1 + j) * P1 + n] = (double)(sgn * f[n + j] / sqrtl(f[n + m] * f[n - m] * f[j + m] * f[j - m]));
+        if (j <= n)
+          h.B[((size_t)m * P1 + n) * P1 + j] =
+              (double)(sqrtl(f[n + m] * f[n - m] / (f[j + m] * f[j - m])) / f[n - j]);
+      }
+  // recurrence constants: am[m], bm[m], c1[n][m], c2[n][m]
+  h.rc.assign(2 * P1 + 2 * P1 * P1, 0.0);
+  for (int m = 1; m <= p; ++m) h.rc[m] = sqrt((2.0 * m - 1.0) / (2.0 * m));
+  for (int m = 0; m <= p; ++m) h.rc[P1 + m] = sqrt(2.0 * m + 1.0);
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m + 2 <= n; ++m) {
+      const double d = sqrt((double)(n + m) * (n - m));
+      h.rc[2 * P1 + n * P1 + m] = (2.0 * n - 1.0) / d;
+      h.rc[2 * P1 + P1 * P1 + n * P1 + m] = sqrt((double)(n + m - 1) * (n - m - 1)) / d;
+    }
+  return h;
+}
+
+std::mutex g_tab_mu;
+std::map<std::pair<int, int>, Tables> g_tabs;  // (device, p) -> tables
+
+template <class T>
+T* upload(const std::vector<T>& v) {
+  T* d = nullptr;
+  const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+  if (hipMalloc((void**)&d, bytes) != hipSuccess) fail(FMM_ENOMEM, "hipMalloc failed for operator tables");
+  HIPCHECK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+}  // namespace
+
+const Tables& tables_for(int p, hipStream_t) {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  auto it = g_tabs.find({dev, p});
+  if (it != g_tabs.end()) return it->second;
+  HostTables h = make_host_tables(p);
+  Tables t;
+  t.p = p;
+  t.J = upload(h.J);
+  t.joff = upload(h.joff);
+  t.A = upload(h.A);
+  t.B = upload(h.B);
+  t.rc = upload(h.rc);
+  return g_tabs.emplace(std::make_pair(dev, p), t).first->second;
+}
+
+// ----------------------------------------------------------------------------
+// device
+// ----------------------------------------------------------------------------
+namespace {
+
+constexpr int kNtMax = (kMaxOrder + 1) * (kMaxOrder + 1);
+
+struct XT {
+  int p;
+  int nt;
+  const double* __restrict__ J;
+  const int* __restrict__ joff;
+  const double* __restrict__ A;
+  const double* __restrict__ B;
+  const double* __restrict__ rc;
+};
+
+XT make_xt(const Tables& t) { return XT{t.p, nterms(t.p), t.J, t.joff, t.A, t.B, t.rc}; }
+
+enum Kind { kM2M = 0, kM2L = 1, kL2L = 2 };
+
+__device__ __forceinline__ void decode(int k, int& n, int& i) {
+  n = (int)sqrtf((float)k);
+  while (n * n > k) --n;
+  while ((n + 1) * (n + 1) <= k) ++n;
+  i = k - n * n;
+}
+
+// Per-wave scratch for one translation.
+struct XScratch {
+  double ca[kMaxOrder + 1], sa[kMaxOrder + 1];  // cos/sin(m alpha)
+  double cb[kMaxOrder + 1], sb[kMaxOrder + 1];  // cos/sin(m beta)
+  double pw[2 * kMaxOrder + 2];                 // rho^-k (M2L) or rho^k (M2M, L2L)
+};
+
+// dst = Rz(sign * gamma) src   (per (c_m, s_m) pair)
+__device__ __forceinline__ void rotz(const double* src, double* dst, int nt, const double* cs, const double* sn,
+                                     double sign) {
+  const int lane = threadIdx.x & 63;
+  for (int k = lane; k < nt; k += 64) {
+    int n, i;
+    decode(k, n, i);
+    if (i == 0) {
+      dst[k] = src[k];
+    } else {
+      const int m = (i + 1) >> 1;
+      const double c = cs[m], s = sign * sn[m];
+      if (i & 1)
+        dst[k] = c * src[k] - s * src[k + 1];
+      else
+        dst[k] = s * src[k - 1] + c * src[k];
+    }
+  }
+}
+
+// dst = J src (trans = false) or J^T src (trans = true), per degree
+__device__ __forceinline__ void applyJ(const double* src, double* dst, const XT& tb, bool trans) {
+  const int lane = threadIdx.x & 63;
+  for (int k = lane; k < tb.nt; k += 64) {
+    int n, i;
+    decode(k, n, i);
+    const int s = 2 * n + 1;
+    const double* Jn = tb.J + tb.joff[n];
+    const double* x = src + n * n;
+    double acc = 0.0;
+    if (!trans) {
+      for (int q = 0; q < s; ++q) acc += Jn[i * s + q] * x[q];
+    } else {
+      for (int q = 0; q < s; ++q) acc += Jn[q * s + i] * x[q];
+    }
+    dst[k] = acc;
+  }
+}
+
+__device__ __forceinline__ int cidx(int n, int m, int t) { return n * n + (m == 0 ? 0 : 2 * m - 1 + t); }
+
+__device__ __forceinline__ void ztrans(const double* src, double* dst, const XT& tb, const double* pw, int kind) {
+  const int lane = threadIdx.x & 63;
+  const int p = tb.p, P1 = p + 1;
+  for (int k = lane; k < tb.nt; k += 64) {
+    int d, i;
+    decode(k, d, i);
+    const int m = (i + 1) >> 1;
+    const int t = (i == 0) ? 0 : ((i & 1) ? 0 : 1);
+    double acc = 0.0;
+    if (kind == kM2L) {
+      const double* Ar = tb.A + ((size_t)m * P1 + d) * P1;
+      for (int n = m; n <= p; ++n) acc += Ar[n] * (pw[n] * src[cidx(n, m, t)]);
+      acc *= pw[d + 1];
+    } else if (kind == kM2M) {
+      const double* Br = tb.B + ((size_t)m * P1 + d) * P1;
+      for (int j = m; j <= d; ++j) acc += Br[j] * (pw[d - j] * src[cidx(j, m, t)]);
+    } else {
+      for (int n = d; n <= p; ++n) acc += tb.B[((size_t)m * P1 + n) * P1 + d] * (pw[n - d] * src[cidx(n, m, t)]);
+    }
+    dst[k] = acc;
+  }
+}
+
+// acc += T(d) X for one translation of the given kind, d = (dx, dy, dz):
+//   M2L: d = source centre - target centre; M2M, L2L: d = child - parent.
+// X is overwritten.  Called by a whole 64-lane workgroup.
+__device__ void translate(int kind, double dx, double dy, double dz, double* X, double* T, double* acc,
+                          const XT& tb, XScratch& sc) {
+  const int lane = threadIdx.x & 63;
+  const int nt = tb.nt, p = tb.p;
+  const double rxy2 = dx * dx + dy * dy;
+  const double rho2 = rxy2 + dz * dz;
+  if (rho2 == 0.0) {  // coincident centres: identity (never for M2L)
+    for (int k = lane; k < nt; k += 64) acc[k] += X[k];
+    __syncthreads();
+    return;
+  }
+  const double rho = sqrt(rho2), rxy = sqrt(rxy2);
+  const double ca1 = dz / rho, sa1 = rxy / rho;
+  const double cb1 = rxy > 0.0 ? dx / rxy : 1.0, sb1 = rxy > 0.0 ? dy / rxy : 0.0;
+  if (lane <= p) {
+    double c = 1.0, s = 0.0, c2 = 1.0, s2 = 0.0;
+    for (int q = 0; q < lane; ++q) {
+      const double cn = c * ca1 - s * sa1, sn = s * ca1 + c * sa1;
+      c = cn;
+      s = sn;
+      const double cn2 = c2 * cb1 - s2 * sb1, sn2 = s2 * cb1 + c2 * sb1;
+      c2 = cn2;
+      s2 = sn2;
+    }
+    sc.ca[lane] = c;
+    sc.sa[lane] = s;
+    sc.cb[lane] = c2;
+    sc.sb[lane] = s2;
+  }
+  if (lane <= 2 * p + 1) {
+    const double base = kind == kM2L ? 1.0 / rho : rho;
+    double v = 1.0;
+    for (int q = 0; q < lane; ++q) v *= base;
+    sc.pw[lane] = v;
+  }
+  __syncthreads();
+  rotz(X, T, nt, sc.cb, sc.sb, -1.0);
+  __syncthreads();
+  applyJ(T, X, tb, true);
+  __syncthreads();
+  rotz(X, T, nt, sc.ca, sc.sa, -1.0);
+  __syncthreads();
+  applyJ(T, X, tb, false);
+  __syncthreads();
+  ztrans(X, T, tb, sc.pw, kind);
+  __syncthreads();
+  applyJ(T, X, tb, true);
+  __syncthreads();
+  rotz(X, T, nt, sc.ca, sc.sa, 1.0);
+  __syncthreads();
+  applyJ(T, X, tb, false);
+  __syncthreads();
+  // acc += Rz(beta) X
+  for (int k = lane; k < nt; k += 64) {
+    int n, i;
+    decode(k, n, i);
+    double v;
+    if (i == 0) {
+      v = X[k];
+    } else {
+      const int m = (i + 1) >> 1;
+      const double c = sc.cb[m], s = sc.sb[m];
+      v = (i & 1) ? (c * X[k] - s * X[k + 1]) : (s * X[k - 1] + c * X[k]);
+    }
+    acc[k] += v;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int level_of(const LevelView& lv, int64_t gid) {
+  int l = 0;
+  while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
+  return l;
+}
+
+// ---- M2L: one 64-lane workgroup per target box of levels 1..L ----
+__global__ __launch_bounds__(64) void k_m2l(LevelView lv, XT tb, const double* __restrict__ Mx,
+                                            double* __restrict__ Lx) {
+  __shared__ double X[kNtMax], T[kNtMax], acc[kNtMax];
+  __shared__ XScratch sc;
+  const int lane = threadIdx.x;
+  const int nt = tb.nt;
+  const int64_t gid = lv.gofs[1] + blockIdx.x;
+  const int l = level_of(lv, gid);
+  const int64_t i = gid - lv.gofs[l];
+  for (int k = lane; k < nt; k += 64) acc[k] = 0.0;
+  const double* gi = lv.geom[l] + i * 10;
+  const double cix = gi[6], ciy = gi[7], ciz = gi[8];
+  const int64_t e0 = lv.w_off[l][i], e1 = lv.w_off[l][i + 1];
+  for (int64_t e = e0; e < e1; ++e) {
+    const int64_t j = lv.w_idx[l][e];
+    const double* gj = lv.geom[l] + j * 10;
+    const double* src = Mx + (size_t)(lv.gofs[l] + j) * nt;
+    for (int k = lane; k < nt; k += 64) X[k] = src[k];
+    __syncthreads();
+    translate(kM2L, gj[6] - cix, gj[7] - ciy, gj[8] - ciz, X, T, acc, tb, sc);
+  }
+  __syncthreads();
+  double* dst = Lx + (size_t)gid * nt;
+  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+}
+
+// ---- M2M: parents of level l-1 from their 8 children on level l ----
+__global__ __launch_bounds__(64) void k_m2m(LevelView lv, int l, XT tb, double* __restrict__ Mx) {
+  __shared__ double X[kNtMax], T[kNtMax], acc[kNtMax];
+  __shared__ XScratch sc;
+  const int lane = threadIdx.x;
+  const int nt = tb.nt;
+  const int64_t par = blockIdx.x;
+  for (int k = lane; k < nt; k += 64) acc[k] = 0.0;
+  const double* gp = lv.geom[l - 1] + par * 10;
+  for (int c = 0; c < 8; ++c) {
+    const int64_t ch = 8 * par + c;
+    const double* gc = lv.geom[l] + ch * 10;
+    const double* src = Mx + (size_t)(lv.gofs[l] + ch) * nt;
+    for (int k = lane; k < nt; k += 64) X[k] = src[k];
+    __syncthreads();
+    translate(kM2M, gc[6] - gp[6], gc[7] - gp[7], gc[8] - gp[8], X, T, acc, tb, sc);
+  }
+  __syncthreads();
+  double* dst = Mx + (size_t)(lv.gofs[l - 1] + par) * nt;
+  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+}
+
+// ---- L2L: children of level l receive their parent's local expansion ----
+__global__ __launch_bounds__(64) void k_l2l(LevelView lv, int l, XT tb, double* __restrict__ Lx) {
+  __shared__ double X[kNtMax], T[kNtMax], acc[kNtMax];
+  __shared__ XScratch sc;
+  const int lane = threadIdx.x;
+  const int nt = tb.nt;
+  const int64_t ch = blockIdx.x;
+  const int64_t par = ch >> 3;
+  const double* gc = lv.geom[l] + ch * 10;
+  const double* gp = lv.geom[l - 1] + par * 10;
+  double* dst = Lx + (size_t)(lv.gofs[l] + ch) * nt;
+  const double* src = Lx + (size_t)(lv.gofs[l - 1] + par) * nt;
+  for (int k = lane; k < nt; k += 64) {
+    acc[k] = dst[k];
+    X[k] = src[k];
+  }
+  __syncthreads();
+  translate(kL2L, gc[6] - gp[6], gc[7] - gp[7], gc[8] - gp[8], X, T, acc, tb, sc);
+  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+}
+
+// ---- P2M: one 64-lane workgroup per leaf, lanes over points ----
+__global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* __restrict__ px,
+                                            const double* __restrict__ py, const double* __restrict__ pz,
+                                            const double* __restrict__ qt, double* __restrict__ Mx) {
+  __shared__ double acc[kNtMax];
+  const int lane = threadIdx.x;
+  const int L = lv.L, p = tb.p, P1 = p + 1, nt = tb.nt;
+  const int64_t b = blockIdx.x;
+  const double* g = lv.geom[L] + b * 10;
+  const double cx = g[6], cy = g[7], cz = g[8];
+  const int s0 = lv.start[L][b], s1 = lv.start[L][b + 1];
+  for (int k = lane; k < nt; k += 64) acc[k] = 0.0;
+  __syncthreads();
+  const double* am = tb.rc;
+  const double* bm = tb.rc + P1;
+  const double* c1 = tb.rc + 2 * P1;
+  const double* c2 = tb.rc + 2 * P1 + P1 * P1;
+  const double s2 = 1.4142135623730951;
+  for (int c0 = s0; c0 < s1; c0 += 64) {
+    const int t = c0 + lane;
+    const bool valid = t < s1;
+    const double x = valid ? px[t] - cx : 0.0;
+    const double y = valid ? py[t] - cy : 0.0;
+    const double z = valid ? pz[t] - cz : 0.0;
+    const double q = valid ? qt[t] : 0.0;
+    const double r2 = x * x + y * y + z * z;
+    double mr = 1.0, mi = 0.0;  // G_m^m
+    for (int m = 0; m <= p; ++m) {
+      if (m > 0) {
+        const double nr = am[m] * (x * mr - y * mi);
+        const double ni = am[m] * (x * mi + y * mr);
+        mr = nr;
+        mi = ni;
+      }
+      double g2r = 0, g2i = 0, g1r = mr, g1i = mi;  // G_{n-2}, G_{n-1}
+      for (int n = m; n <= p; ++n) {
+        double gr, gi;
+        if (n == m) {
+          gr = mr;
+          gi = mi;
+        } else if (n == m + 1) {
+          gr = bm[m] * z * mr;
+          gi = bm[m] * z * mi;
+        } else {
+          gr = c1[n * P1 + m] * z * g1r - c2[n * P1 + m] * r2 * g2r;
+          gi = c1[n * P1 + m] * z * g1i - c2[n * P1 + m] * r2 * g2i;
+        }
+        if (n > m) {
+          g2r = g1r;
+          g2i = g1i;
+          g1r = gr;
+          g1i = gi;
+        }
+        double vc = (m == 0 ? 1.0 : s2) * q * gr;
+        double vs = s2 * q * gi;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          vc += __shfl_xor(vc, d);
+          vs += __shfl_xor(vs, d);
+        }
+        if (lane == 0) {
+          acc[cidx(n, m, 0)] += vc;
+          if (m > 0) acc[cidx(n, m, 1)] += vs;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double* dst = Mx + (size_t)(lv.gofs[L] + b) * nt;
+  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+}
+
+// ---- L2P: far field at the points of each leaf (phi and E = -grad phi) ----
+__global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const double* __restrict__ px,
+                                            const double* __restrict__ py, const double* __restrict__ pz,
+                                            const double* __restrict__ Lx, double* __restrict__ fphi,
+                                            double* __restrict__ fex, double* __restrict__ fey,
+                                            double* __restrict__ fez) {
+  const int lane = threadIdx.x;
+  const int L = lv.L, p = tb.p, P1 = p + 1, nt = tb.nt;
+  const int64_t b = blockIdx.x;
+  const double* g = lv.geom[L] + b * 10;
+  const double cx = g[6], cy = g[7], cz = g[8];
+  const int s0 = lv.start[L][b], s1 = lv.start[L][b + 1];
+  const double* Lc = Lx + (size_t)(lv.gofs[L] + b) * nt;
+  const double* am = tb.rc;
+  const double* bm = tb.rc + P1;
+  const double* c1 = tb.rc + 2 * P1;
+  const double* c2 = tb.rc + 2 * P1 + P1 * P1;
+  const double s2 = 1.4142135623730951;
+  for (int c0 = s0; c0 < s1; c0 += 64) {
+    const int t = c0 + lane;
+    if (t >= s1) break;
+    const double x = px[t] - cx, y = py[t] - cy, z = pz[t] - cz;
+    const double r2 = x * x + y * y + z * z;
+    // G and its gradient (complex): value, d/dx, d/dy, d/dz
+    double mr = 1.0, mi = 0.0, mxr = 0, mxi = 0, myr = 0, myi = 0, mzr = 0, mzi = 0;
+    double f = 0, fx = 0, fy = 0, fz = 0;
+    for (int m = 0; m <= p; ++m) {
+      if (m > 0) {
+        const double a = am[m];
+        // G = a (x + i y) Gp;  dG = a [(1, i, 0) Gp + (x + i y) dGp]
+        const double nr = a * (x * mr - y * mi), ni = a * (x * mi + y * mr);
+        const double nxr = a * (mr + x * mxr - y * mxi), nxi = a * (mi + x * mxi + y * mxr);
+        const double nyr = a * (-mi + x * myr - y * myi), nyi = a * (mr + x * myi + y * myr);
+        const double nzr = a * (x * mzr - y * mzi), nzi = a * (x * mzi + y * mzr);
+        mr = nr; mi = ni; mxr = nxr; mxi = nxi; myr = nyr; myi = nyi; mzr = nzr; mzi = nzi;
+      }
+      double g1[8] = {mr, mi, mxr, mxi, myr, myi, mzr, mzi};
+      double g2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int n = m; n <= p; ++n) {
+        double gn[8];
+        if (n == m) {
+          for (int u = 0; u < 8; ++u) gn[u] = g1[u];
+        } else if (n == m + 1) {
+          const double bb = bm[m];
+          gn[0] = bb * z * mr; gn[1] = bb * z * mi;
+          gn[2] = bb * z * mxr; gn[3] = bb * z * mxi;
+          gn[4] = bb * z * myr; gn[5] = bb * z * myi;
+          gn[6] = bb * (mr + z * mzr); gn[7] = bb * (mi + z * mzi);
+        } else {
+          const double a1 = c1[n * P1 + m], a2 = c2[n * P1 + m];
+          gn[0] = a1 * z * g1[0] - a2 * r2 * g2[0];
+          gn[1] = a1 * z * g1[1] - a2 * r2 * g2[1];
+          gn[2] = a1 * z * g1[2] - a2 * (r2 * g2[2] + 2.0 * x * g2[0]);
+          gn[3] = a1 * z * g1[3] - a2 * (r2 * g2[3] + 2.0 * x * g2[1]);
+          gn[4] = a1 * z * g1[4] - a2 * (r2 * g2[4] + 2.0 * y * g2[0]);
+          gn[5] = a1 * z * g1[5] - a2 * (r2 * g2[5] + 2.0 * y * g2[1]);
+          gn[6] = a1 * (g1[0] + z * g1[6]) - a2 * (r2 * g2[6] + 2.0 * z * g2[0]);
+          gn[7] = a1 * (g1[1] + z * g1[7]) - a2 * (r2 * g2[7] + 2.0 * z * g2[1]);
+        }
+        if (n > m) {
+          for (int u = 0; u < 8; ++u) {
+            g2[u] = g1[u];
+            g1[u] = gn[u];
+          }
+        }
+        const double lc = Lc[cidx(n, m, 0)] * (m == 0 ? 1.0 : s2);
+        const double ls = m == 0 ? 0.0 : Lc[cidx(n, m, 1)] * s2;
+        f += lc * gn[0] + ls * gn[1];
+        fx += lc * gn[2] + ls * gn[3];
+        fy += lc * gn[4] + ls * gn[5];
+        fz += lc * gn[6] + ls * gn[7];
+      }
+    }
+    fphi[t] = f;
+    fex[t] = -fx;
+    fey[t] = -fy;
+    fez[t] = -fz;
+  }
+}
+
+}  // namespace
+
+// launch helpers used by evaluate() (p2p.hip)
+void launch_p2m(const Tree& t, const Tables& tb, const double* qt, double* Mx, hipStream_t s) {
+  k_p2m<<<(unsigned)t.lev[t.L].nbox, 64, 0, s>>>(t.view(), make_xt(tb), t.px, t.py, t.pz, qt, Mx);
+  HIPCHECK(hipGetLastError());
+}
+void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s) {
+  k_m2m<<<(unsigned)t.lev[l - 1].nbox, 64, 0, s>>>(t.view(), l, make_xt(tb), Mx);
+  HIPCHECK(hipGetLastError());
+}
+void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
+  const int64_t nb = t.nbox_total - 1;  // levels 1..L
+  k_m2l<<<(unsigned)nb, 64, 0, s>>>(t.view(), make_xt(tb), Mx, Lx);
+  HIPCHECK(hipGetLastError());
+}
+void launch_l2l(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s) {
+  k_l2l<<<(unsigned)t.lev[l].nbox, 64, 0, s>>>(t.view(), l, make_xt(tb), Lx);
+  HIPCHECK(hipGetLastError());
+}
+void launch_l2p(const Tree& t, const Tables& tb, const double* Lx, double* f0, double* f1, double* f2, double* f3,
+                hipStream_t s) {
+  k_l2p<<<(unsigned)t.lev[t.L].nbox, 64, 0, s>>>(t.view(), make_xt(tb), t.px, t.py, t.pz, Lx, f0, f1, f2, f3);
+  HIPCHECK(hipGetLastError());
+}
+
+}  // namespace fmm

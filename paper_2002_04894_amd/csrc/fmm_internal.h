@@ -1,0 +1,106 @@
+// Internal declarations of the gfx950 FMM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+constexpr int kWave = 64;
+constexpr int kMaxLevels = FMM_MAX_LEVELS;
+constexpr int kMaxOrder = FMM_MAX_ORDER;
+
+inline int nterms(int p) { return (p + 1) * (p + 1); }
+
+// Error carrying a status code; caught at the ABI boundary.
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+#define HIPCHECK(x) ::fmm::check_hip((x), #x)
+
+// Stream-ordered device allocation (pooled).
+void* dalloc(size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+
+// Per-level box geometry / lists in device memory.
+struct Level {
+  int64_t nbox = 0;
+  int64_t gofs = 0;           // global box id of box 0 of this level
+  double* geom = nullptr;     // nbox x 10: lo[3], hi[3], centre[3], radius
+  int32_t* start = nullptr;   // nbox + 1 point offsets (tree order)
+  int64_t* s_off = nullptr;   // strong CSR (local box indices)
+  int32_t* s_idx = nullptr;
+  int64_t s_nnz = 0;
+  int64_t* w_off = nullptr;   // weak CSR (local box indices)
+  int32_t* w_idx = nullptr;
+  int64_t w_nnz = 0;
+};
+
+// Device-side view of all levels, passed by value to kernels.
+struct LevelView {
+  int L;
+  int64_t gofs[kMaxLevels + 2];
+  const double* geom[kMaxLevels + 1];
+  const int32_t* start[kMaxLevels + 1];
+  const int64_t* s_off[kMaxLevels + 1];
+  const int32_t* s_idx[kMaxLevels + 1];
+  const int64_t* w_off[kMaxLevels + 1];
+  const int32_t* w_idx[kMaxLevels + 1];
+};
+
+struct Tree {
+  int64_t n = 0;
+  int L = 0;
+  double theta = 0;
+  hipStream_t stream = nullptr;
+  // points in tree order
+  double* px = nullptr;
+  double* py = nullptr;
+  double* pz = nullptr;
+  int32_t* perm = nullptr;
+  std::vector<Level> lev;     // 0..L
+  int64_t nbox_total = 0;     // sum over levels 0..L
+  int64_t m2l_pairs = 0;
+  int64_t p2p_pairs = 0;
+  LevelView view() const;
+};
+
+// Fixed operator tables of one expansion order p (device memory).
+struct Tables {
+  int p = -1;
+  double* J = nullptr;     // per degree n a (2n+1)^2 row-major block at joff[n]
+  int* joff = nullptr;     // p + 2 offsets
+  double* A = nullptr;     // M2L along z: A[(m*(p+1) + j)*(p+1) + n]
+  double* B = nullptr;     // M2M / L2L along z: B[(m*(p+1) + n)*(p+1) + j]
+  double* rc = nullptr;    // recurrence constants, see expansions.hip
+};
+const Tables& tables_for(int p, hipStream_t s);
+
+// Phase timer (HIP events), per thread.
+struct PhaseTimer {
+  void begin(int phase, hipStream_t s);
+  void end(int phase, hipStream_t s);
+  void reset();
+};
+PhaseTimer& timer();
+
+// ---- launch wrappers ----
+void tree_build(Tree& t, const double* x, const double* y, const double* z, hipStream_t s);
+void lists_build(Tree& t, hipStream_t s);
+void tree_compute_stats(Tree& t, hipStream_t s);
+void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, double* ex, double* ey, double* ez,
+              hipStream_t s);
+
+// exclusive scan of int32 counts into int64 offsets (out[n] = total + base)
+void scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t base, hipStream_t s);
+
+}  // namespace fmm

@@ -1,0 +1,422 @@
+// Balanced tree by median splits (Section 2.1.2 with eta = 1, Algorithm 2 on
+// one process), built on the GPU.
+//
+// Every box of level l < L is split into 8 by three successive bisections;
+// bisection round k (k = 0 .. 3L-1) works on the 2^k segments of depth k.
+// A segment is one contiguous range of points in tree order.  Per segment:
+//   * axis = longest edge of its cell (ties: x, then y, then z);
+//   * the rank-floor(n/2) point in the total order (coordinate, original
+//     index) is found by an MSB radix select on order-preserving 64-bit keys
+//     of the coordinate (the bits shared by the cell's two bounds are skipped;
+//     ties are broken by position, which is ascending original index because
+//     every partition is stable);
+//   * a stable partition moves the low side in front of the high side;
+//   * the split plane is the midpoint of the two middle coordinates (the
+//     point's coordinate for one point, the cell midpoint for none).
+// Child cells are the parent cell cut at the plane; the child number is
+// 4*b1 + 2*b2 + b3 with b = 1 for the high side, so the segment index at
+// depth 3l is the box index at level l.
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+
+__device__ __forceinline__ uint64_t okey(double c) {
+  // order-preserving bit pattern; -0.0 is read as +0.0
+  const uint64_t b = (uint64_t)__double_as_longlong(c + 0.0);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void k_canon_copy(const double* __restrict__ x, const double* __restrict__ y,
+                             const double* __restrict__ z, double* __restrict__ ox, double* __restrict__ oy,
+                             double* __restrict__ oz, int32_t* __restrict__ oid, int64_t n, int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = x[i] + 0.0, b = y[i] + 0.0, c = z[i] + 0.0;
+  const double lim = 1e300;
+  if (!(fabs(a) <= lim && fabs(b) <= lim && fabs(c) <= lim)) atomicOr(bad, 1);
+  ox[i] = a;
+  oy[i] = b;
+  oz[i] = c;
+  oid[i] = (int32_t)i;
+}
+
+// min / max of the three coordinates: per-block partials, then one block
+__global__ void k_bbox_partial(const double* __restrict__ x, const double* __restrict__ y,
+                               const double* __restrict__ z, int64_t n, double* __restrict__ part) {
+  __shared__ double sm[6][4];
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = x[i], b = y[i], c = z[i];
+    v[0] = fmin(v[0], a); v[1] = fmin(v[1], b); v[2] = fmin(v[2], c);
+    v[3] = fmax(v[3], a); v[4] = fmax(v[4], b); v[5] = fmax(v[5], c);
+  }
+  for (int d = 32; d >= 1; d >>= 1)
+    for (int k = 0; k < 6; ++k) {
+      const double o = __shfl_xor(v[k], d);
+      v[k] = k < 3 ? fmin(v[k], o) : fmax(v[k], o);
+    }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) sm[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    double r = sm[k][0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = k < 3 ? fmin(r, sm[k][w]) : fmax(r, sm[k][w]);
+    part[blockIdx.x * 6 + k] = r;
+  }
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nparts, int64_t n, double* __restrict__ cells,
+                             int32_t* __restrict__ seg_start, int32_t* __restrict__ seg_n) {
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    double r = part[k];
+    for (int i = 1; i < nparts; ++i) r = k < 3 ? fmin(r, part[i * 6 + k]) : fmax(r, part[i * 6 + k]);
+    cells[k] = r;
+  }
+  if (threadIdx.x == 0) {
+    seg_start[0] = 0;
+    seg_n[0] = (int32_t)n;
+  }
+}
+
+// exclusive block scan of ints; also returns the block total
+template <int BS>
+__device__ __forceinline__ int block_excl_scan(int v, int* sm, int& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(inc, d);
+    if (lane >= d) inc += t;
+  }
+  if constexpr (BS == 64) {
+    total = __shfl(inc, 63);
+    return inc - v;
+  } else {
+    if (lane == 63) sm[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BS / 64; ++w) {
+      const int s = sm[w];
+      off += (w < wid) ? s : 0;
+      tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+  }
+}
+
+template <int BS>
+__device__ __forceinline__ double block_reduce(double v, bool is_max, double* sm) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const double o = __shfl_xor(v, d);
+    v = is_max ? fmax(v, o) : fmin(v, o);
+  }
+  if constexpr (BS == 64) {
+    return v;
+  } else {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sm[wid] = v;
+    __syncthreads();
+    double r = sm[0];
+#pragma unroll
+    for (int w = 1; w < BS / 64; ++w) r = is_max ? fmax(r, sm[w]) : fmin(r, sm[w]);
+    __syncthreads();
+    return r;
+  }
+}
+
+struct SelState {
+  uint64_t prefix;
+  int shift;
+  int rank;
+  int cnt;
+};
+
+// One bisection round: block b handles segment b of depth `depth`.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_orb_round(
+    const double* __restrict__ xin, const double* __restrict__ yin, const double* __restrict__ zin,
+    const int32_t* __restrict__ iin, double* __restrict__ xout, double* __restrict__ yout, double* __restrict__ zout,
+    int32_t* __restrict__ iout, double* __restrict__ cells, int32_t* __restrict__ seg_start,
+    int32_t* __restrict__ seg_n, int depth) {
+#pragma clang fp contract(off)
+  __shared__ unsigned hist[256];
+  __shared__ SelState st;
+  __shared__ int scan_sm[BS / 64 + 1];
+  __shared__ double red_sm[BS / 64 + 1];
+  const int tid = threadIdx.x;
+  const int64_t base = ((int64_t)1 << depth) - 1;
+  const int64_t seg = base + blockIdx.x;
+  const int start = seg_start[seg];
+  const int n = seg_n[seg];
+  double lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = cells[seg * 6 + a];
+    hi[a] = cells[seg * 6 + 3 + a];
+  }
+  int axis = 0;
+  double ext = hi[0] - lo[0];
+  if (hi[1] - lo[1] > ext) { ext = hi[1] - lo[1]; axis = 1; }
+  if (hi[2] - lo[2] > ext) { ext = hi[2] - lo[2]; axis = 2; }
+  const double* cin = axis == 0 ? xin : (axis == 1 ? yin : zin);
+  const int m = n / 2;
+  double plane;
+
+  if (n < 2) {
+    if (n == 1) {
+      // lone point: goes to the high side, the plane passes through it
+      if (tid == 0) {
+        xout[start] = xin[start];
+        yout[start] = yin[start];
+        zout[start] = zin[start];
+        iout[start] = iin[start];
+      }
+      plane = cin[start];
+    } else {
+      plane = 0.5 * (lo[axis] + hi[axis]);
+    }
+  } else {
+    // ---- radix select of the rank-m key ----
+    if (tid == 0) {
+      const uint64_t klo = okey(lo[axis]), khi = okey(hi[axis]);
+      const uint64_t dif = klo ^ khi;
+      const int sh = dif ? __clzll((long long)dif) : 64;
+      st.shift = sh;
+      st.prefix = sh == 0 ? 0ull : (klo >> (64 - sh));
+      st.rank = m;
+      st.cnt = n;
+    }
+    __syncthreads();
+    while (true) {
+      const int shift = st.shift;
+      const int cnt = st.cnt;
+      const uint64_t prefix = st.prefix;
+      if (cnt <= 1 || shift >= 64) break;
+      const int D = min(8, 64 - shift);
+      for (int i = tid; i < 256; i += BS) hist[i] = 0u;
+      __syncthreads();
+      for (int i = tid; i < n; i += BS) {
+        const uint64_t k = okey(cin[start + i]);
+        const bool match = (shift == 0) || ((k >> (64 - shift)) == prefix);
+        if (match) atomicAdd(&hist[(unsigned)((k << shift) >> (64 - D))], 1u);
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const int lane = tid;
+        unsigned h[4];
+        unsigned s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          h[q] = hist[lane * 4 + q];
+          s += h[q];
+        }
+        unsigned inc = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const unsigned t = __shfl_up(inc, d);
+          if (lane >= d) inc += t;
+        }
+        const unsigned exc = inc - s;
+        const unsigned r = (unsigned)st.rank;
+        if (s > 0 && exc <= r && r < inc) {
+          unsigned before = exc;
+          int q = 0;
+          while (before + h[q] <= r) {
+            before += h[q];
+            ++q;
+          }
+          st.prefix = (prefix << D) | (uint64_t)(lane * 4 + q);
+          st.shift = shift + D;
+          st.rank = (int)(r - before);
+          st.cnt = (int)h[q];
+        }
+      }
+      __syncthreads();
+    }
+    const int shift = st.shift;
+    const uint64_t prefix = st.prefix;
+    const int rank = st.rank;
+
+    // ---- stable partition: low = key-prefix below, or equal and early ----
+    int low_base = 0, eq_base = 0;
+    double cmax_low = -INFINITY, cmin_high = INFINITY;
+    for (int c0 = 0; c0 < n; c0 += BS) {
+      const int i = c0 + tid;
+      const bool valid = i < n;
+      double cx = 0, cy = 0, cz = 0, cc = 0;
+      int id = 0;
+      bool less = false, match = false;
+      if (valid) {
+        cx = xin[start + i];
+        cy = yin[start + i];
+        cz = zin[start + i];
+        id = iin[start + i];
+        cc = axis == 0 ? cx : (axis == 1 ? cy : cz);
+        const uint64_t k = okey(cc);
+        const uint64_t top = k >> (64 - shift);  // shift >= 1 here
+        less = top < prefix;
+        match = top == prefix;
+      }
+      int eq_tot;
+      const int eqr = block_excl_scan<BS>(match ? 1 : 0, scan_sm, eq_tot);
+      const bool low = valid && (less || (match && (eq_base + eqr) < rank));
+      int low_tot;
+      const int lr = block_excl_scan<BS>(low ? 1 : 0, scan_sm, low_tot);
+      if (valid) {
+        int dst;
+        if (low) {
+          dst = start + low_base + lr;
+          cmax_low = fmax(cmax_low, cc);
+        } else {
+          dst = start + m + (i - (low_base + lr));
+          cmin_high = fmin(cmin_high, cc);
+        }
+        // low positions stay below start + m and high ones below start + n
+        // whenever the selection is right; the guard keeps a wrong selection
+        // from writing outside this segment (parity tests would flag it)
+        if ((low && dst < start + m) || (!low && dst < start + n)) {
+          xout[dst] = cx;
+          yout[dst] = cy;
+          zout[dst] = cz;
+          iout[dst] = id;
+        }
+      }
+      low_base += low_tot;
+      eq_base += eq_tot;
+    }
+    cmax_low = block_reduce<BS>(cmax_low, true, red_sm);
+    cmin_high = block_reduce<BS>(cmin_high, false, red_sm);
+    plane = 0.5 * (cmax_low + cmin_high);
+  }
+
+  if (tid == 0) {
+    const int64_t cb = ((int64_t)1 << (depth + 1)) - 1 + 2 * (int64_t)blockIdx.x;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cells[cb * 6 + a] = lo[a];
+      cells[cb * 6 + 3 + a] = hi[a];
+      cells[(cb + 1) * 6 + a] = lo[a];
+      cells[(cb + 1) * 6 + 3 + a] = hi[a];
+    }
+    cells[cb * 6 + 3 + axis] = plane;
+    cells[(cb + 1) * 6 + axis] = plane;
+    seg_start[cb] = start;
+    seg_n[cb] = m;
+    seg_start[cb + 1] = start + m;
+    seg_n[cb + 1] = n - m;
+  }
+}
+
+// centre = cell centre, radius = half the cell diagonal (Section 2.1.1)
+__global__ void k_box_geom(const double* __restrict__ cells, const int32_t* __restrict__ seg_start, int depth,
+                           int64_t nbox, double* __restrict__ geom, int32_t* __restrict__ start, int32_t n) {
+#pragma clang fp contract(off)
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nbox) return;
+  if (b == nbox) {
+    start[nbox] = n;
+    return;
+  }
+  const int64_t c = ((int64_t)1 << depth) - 1 + b;
+  double d[3];
+  for (int a = 0; a < 3; ++a) {
+    const double lo = cells[c * 6 + a], hi = cells[c * 6 + 3 + a];
+    geom[b * 10 + a] = lo;
+    geom[b * 10 + 3 + a] = hi;
+    geom[b * 10 + 6 + a] = 0.5 * (lo + hi);
+    d[a] = hi - lo;
+  }
+  geom[b * 10 + 9] = 0.5 * sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+  start[b] = seg_start[c];
+}
+
+}  // namespace
+
+void tree_build(Tree& t, const double* x, const double* y, const double* z, hipStream_t s) {
+  const int64_t n = t.n;
+  const int L = t.L;
+  double* xs[2];
+  double* ys[2];
+  double* zs[2];
+  int32_t* ids[2];
+  for (int k = 0; k < 2; ++k) {
+    xs[k] = (double*)dalloc(n * sizeof(double), s);
+    ys[k] = (double*)dalloc(n * sizeof(double), s);
+    zs[k] = (double*)dalloc(n * sizeof(double), s);
+    ids[k] = (int32_t*)dalloc(n * sizeof(int32_t), s);
+  }
+  const int64_t nseg = ((int64_t)2 << (3 * L)) - 1;  // depths 0 .. 3L
+  double* cells = (double*)dalloc(nseg * 6 * sizeof(double), s);
+  int32_t* seg_start = (int32_t*)dalloc(nseg * sizeof(int32_t), s);
+  int32_t* seg_n = (int32_t*)dalloc(nseg * sizeof(int32_t), s);
+  int* bad = (int*)dalloc(sizeof(int), s);
+  HIPCHECK(hipMemsetAsync(bad, 0, sizeof(int), s));
+
+  const int nb = (int)((n + 255) / 256);
+  k_canon_copy<<<nb, 256, 0, s>>>(x, y, z, xs[0], ys[0], zs[0], ids[0], n, bad);
+  HIPCHECK(hipGetLastError());
+  const int nparts = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  double* part = (double*)dalloc((size_t)nparts * 6 * sizeof(double), s);
+  k_bbox_partial<<<nparts, 256, 0, s>>>(xs[0], ys[0], zs[0], n, part);
+  HIPCHECK(hipGetLastError());
+  k_bbox_final<<<1, 64, 0, s>>>(part, nparts, n, cells, seg_start, seg_n);
+  HIPCHECK(hipGetLastError());
+  dfree(part, s);
+
+  int cur = 0;
+  for (int depth = 0; depth < 3 * L; ++depth) {
+    const int64_t nsegd = (int64_t)1 << depth;
+    const int64_t maxn = (n + nsegd - 1) / nsegd;
+    const int o = cur ^ 1;
+    if (maxn > 128)
+      k_orb_round<256><<<(unsigned)nsegd, 256, 0, s>>>(xs[cur], ys[cur], zs[cur], ids[cur], xs[o], ys[o], zs[o],
+                                                       ids[o], cells, seg_start, seg_n, depth);
+    else
+      k_orb_round<64><<<(unsigned)nsegd, 64, 0, s>>>(xs[cur], ys[cur], zs[cur], ids[cur], xs[o], ys[o], zs[o],
+                                                     ids[o], cells, seg_start, seg_n, depth);
+    HIPCHECK(hipGetLastError());
+    cur = o;
+  }
+
+  t.lev.assign(L + 1, Level());
+  int64_t g = 0;
+  for (int l = 0; l <= L; ++l) {
+    Level& V = t.lev[l];
+    V.nbox = (int64_t)1 << (3 * l);
+    V.gofs = g;
+    g += V.nbox;
+    V.geom = (double*)dalloc(V.nbox * 10 * sizeof(double), s);
+    V.start = (int32_t*)dalloc((V.nbox + 1) * sizeof(int32_t), s);
+    k_box_geom<<<(unsigned)((V.nbox + 1 + 255) / 256), 256, 0, s>>>(cells, seg_start, 3 * l, V.nbox, V.geom,
+                                                                    V.start, (int32_t)n);
+    HIPCHECK(hipGetLastError());
+  }
+  t.nbox_total = g;
+  t.px = xs[cur];
+  t.py = ys[cur];
+  t.pz = zs[cur];
+  t.perm = ids[cur];
+  dfree(xs[cur ^ 1], s);
+  dfree(ys[cur ^ 1], s);
+  dfree(zs[cur ^ 1], s);
+  dfree(ids[cur ^ 1], s);
+  dfree(cells, s);
+  dfree(seg_start, s);
+  dfree(seg_n, s);
+
+  int hbad = 0;
+  HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  dfree(bad, s);
+  if (hbad) fail(FMM_EINVAL, "non-finite coordinate or |coordinate| > 1e300");
+}
+
+}  // namespace fmm

@@ -1,0 +1,204 @@
+"""ctypes binding of libfmm.so (the C ABI in include/fmm.h).
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of libfmm.so.  Device arrays are torch CUDA (HIP) float64 tensors; the
+stream is torch's current stream unless one is given.  There is no CPU
+fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
+FMM_PART_NEAR, FMM_PART_FAR, FMM_PART_ALL = 1, 2, 3
+PHASES = ("tree", "lists", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
+MAX_LEVELS, MAX_ORDER = 8, 20
+
+_lib = None
+
+
+class FMMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fmm error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2002_04894_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    L.fmm_build.argtypes = [vp, vp, vp, i64, i32, d, vp, C.POINTER(vp)]
+    L.fmm_evaluate_tree.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+    L.fmm_evaluate_tree_parts.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+    L.fmm_evaluate.argtypes = [vp, vp, vp, vp, i64, d, i32, i32, vp, vp, vp, vp, vp]
+    L.fmm_free.argtypes = [vp]
+    L.fmm_last_error.argtypes = []
+    L.fmm_last_error.restype = C.c_char_p
+    L.fmm_tree_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(d)]
+    L.fmm_tree_perm.argtypes = [vp, vp]
+    L.fmm_tree_boxes.argtypes = [vp, i32, vp, vp]
+    L.fmm_tree_lists.argtypes = [vp, i32, i32, C.POINTER(i64), vp, vp]
+    L.fmm_tree_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+    L.fmm_set_profiling.argtypes = [i32]
+    L.fmm_last_timings.argtypes = [vp]
+    L.fmm_bytes_estimate.argtypes = [i64, i32, d, i32]
+    L.fmm_bytes_estimate.restype = C.c_size_t
+    for f in ("fmm_build", "fmm_evaluate_tree", "fmm_evaluate_tree_parts", "fmm_evaluate", "fmm_free",
+              "fmm_tree_info", "fmm_tree_perm", "fmm_tree_boxes", "fmm_tree_lists", "fmm_tree_stats",
+              "fmm_set_profiling", "fmm_last_timings"):
+        getattr(L, f).restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != FMM_OK:
+        raise FMMError(rc, lib().fmm_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return int(t)
+
+
+def _dev(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 tensor on a HIP device")
+    return t
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Tree:
+    """Owning wrapper of an fmm_tree handle."""
+
+    def __init__(self, handle: int, n: int):
+        self.handle = handle
+        self.n = n
+
+    def free(self):
+        if self.handle:
+            _check(lib().fmm_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fmm_build(x, y, z, levels: int, theta: float, stream=None) -> Tree:
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _dev(t, nm)
+    h = C.c_void_p()
+    _check(lib().fmm_build(_ptr(x), _ptr(y), _ptr(z), x.numel(), int(levels), float(theta), _stream(stream),
+                           C.byref(h)))
+    return Tree(h.value, x.numel())
+
+
+def fmm_evaluate_tree(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts: int = FMM_PART_ALL):
+    for t, nm in ((q, "q"), (pot, "pot"), (ex, "ex"), (ey, "ey"), (ez, "ez")):
+        _dev(t, nm)
+        if t.numel() != tree.n:
+            raise ValueError(f"{nm} must have {tree.n} elements")
+    if parts == FMM_PART_ALL:
+        _check(lib().fmm_evaluate_tree(tree.handle, _ptr(q), int(p), _ptr(pot), _ptr(ex), _ptr(ey), _ptr(ez),
+                                       _stream(stream)))
+    else:
+        _check(lib().fmm_evaluate_tree_parts(tree.handle, _ptr(q), int(p), int(parts), _ptr(pot), _ptr(ex),
+                                             _ptr(ey), _ptr(ez), _stream(stream)))
+
+
+def fmm_evaluate(x, y, z, q, theta: float, p: int, levels: int, pot, ex, ey, ez, stream=None):
+    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (q, "q"), (pot, "pot"), (ex, "ex"), (ey, "ey"), (ez, "ez")):
+        _dev(t, nm)
+        if t.numel() != x.numel():
+            raise ValueError(f"{nm} must have {x.numel()} elements")
+    _check(lib().fmm_evaluate(_ptr(x), _ptr(y), _ptr(z), _ptr(q), x.numel(), float(theta), int(p), int(levels),
+                              _ptr(pot), _ptr(ex), _ptr(ey), _ptr(ez), _stream(stream)))
+
+
+def fmm_free(tree: Tree):
+    tree.free()
+
+
+def fmm_last_error() -> str:
+    return lib().fmm_last_error().decode()
+
+
+def fmm_tree_info(tree: Tree):
+    n, lv, th = C.c_int64(), C.c_int(), C.c_double()
+    _check(lib().fmm_tree_info(tree.handle, C.byref(n), C.byref(lv), C.byref(th)))
+    return n.value, lv.value, th.value
+
+
+def fmm_tree_perm(tree: Tree) -> np.ndarray:
+    out = np.empty(tree.n, dtype=np.int32)
+    _check(lib().fmm_tree_perm(tree.handle, out.ctypes.data))
+    return out
+
+
+def fmm_tree_boxes(tree: Tree, level: int):
+    nb = 8 ** level
+    geom = np.empty((nb, 10))
+    start = np.empty(nb + 1, dtype=np.int64)
+    _check(lib().fmm_tree_boxes(tree.handle, int(level), geom.ctypes.data, start.ctypes.data))
+    return geom, start
+
+
+def fmm_tree_lists(tree: Tree, level: int, kind: int):
+    nnz = C.c_int64()
+    _check(lib().fmm_tree_lists(tree.handle, int(level), int(kind), C.byref(nnz), None, None))
+    off = np.empty(8 ** level + 1, dtype=np.int64)
+    idx = np.empty(max(nnz.value, 1), dtype=np.int32)
+    _check(lib().fmm_tree_lists(tree.handle, int(level), int(kind), C.byref(nnz), off.ctypes.data, idx.ctypes.data))
+    return off, idx[: nnz.value]
+
+
+def fmm_tree_stats(tree: Tree):
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib().fmm_tree_stats(tree.handle, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def fmm_set_profiling(on: bool):
+    _check(lib().fmm_set_profiling(1 if on else 0))
+
+
+def fmm_last_timings() -> dict:
+    ms = np.zeros(len(PHASES))
+    _check(lib().fmm_last_timings(ms.ctypes.data))
+    return dict(zip(PHASES, ms.tolist()))
+
+
+def fmm_bytes_estimate(n: int, levels: int, theta: float, p: int) -> int:
+    return int(lib().fmm_bytes_estimate(int(n), int(levels), float(theta), int(p)))
+
+
+def evaluate(x, y, z, q, levels: int, theta: float, p: int, stream=None):
+    """Convenience: allocate outputs and run the one-shot evaluation."""
+    import torch
+    pot, ex, ey, ez = (torch.empty_like(x) for _ in range(4))
+    fmm_evaluate(x, y, z, q, theta, p, levels, pot, ex, ey, ez, stream)
+    return pot, ex, ey, ez
