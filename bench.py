@@ -1,0 +1,178 @@
+"""Throughput of the balanced-tree FMM evaluation pass on one MI355X.
+
+One step = fmm_build + fmm_evaluate_tree + fmm_free (tree, lists, P2M, M2M,
+M2L, L2L, L2P, P2P) on the 2^20-point Gaussian-mixture cloud (5 levels,
+theta 0.5, p 15, FP64), with inputs and outputs resident in HBM.  Prints one
+JSON line.  `value` = points per second of the whole step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2002_04894_amd import fmm, workloads  # noqa: E402
+
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (and matrix) peak
+HBM_PEAK_GBS = 8000.0
+
+
+def m2l_flops_per_pair(p: int) -> int:
+    """Algorithmic flops of one rotational M2L (Section 2.1.3): two rotations
+    with dense per-degree blocks, sum_n (2n+1)^2 multiply-adds each, plus the
+    z-axis translation, sum_m (p+1-|m|)^2 multiply-adds; 2 flops each."""
+    rot = sum((2 * n + 1) ** 2 for n in range(p + 1))
+    zt = sum((p + 1 - abs(m)) ** 2 for m in range(-p, p + 1))
+    return 2 * (2 * rot + zt)
+
+
+def p2p_flops_per_pair() -> int:
+    """Near-field interaction: 3 sub, 5 for r^2, 1 rsqrt, 9 for phi and E."""
+    return 20
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gmix1m")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    x, y, z, q, w = workloads.workload(args.workload)
+    n, L, theta, p = x.shape[0], w["levels"], w["theta"], w["p"]
+    dev = lambda a: torch.from_numpy(a).to("cuda")  # noqa: E731
+    X, Y, Z, Q = dev(x), dev(y), dev(z), dev(q)
+    outs = [torch.empty_like(X) for _ in range(4)]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        t = fmm.fmm_build(X, Y, Z, L, theta, stream)
+        fmm.fmm_evaluate_tree(t, Q, p, *outs, stream)
+        return t
+
+    fmm.fmm_set_profiling(True)
+    for _ in range(args.warmup):
+        step().free()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    phase_sum = {k: 0.0 for k in fmm.PHASES}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    last = None
+    for _ in range(args.steps):
+        tr = step()
+        ph = fmm.fmm_last_timings()
+        for k in phase_sum:
+            phase_sum[k] += ph[k]
+        if last is not None:
+            last.free()
+        last = tr
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    m2l_pairs, p2p_pairs = fmm.fmm_tree_stats(last)
+    last.free()
+    ms_step = ms_total / args.steps
+    phase_avg = {k: v / args.steps for k, v in phase_sum.items()}
+
+    # dominant kernel: M2L (one launch per step)
+    m2l_ms = phase_avg["m2l"]
+    m2l_flops = m2l_pairs * m2l_flops_per_pair(p)
+    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0
+    roofline = {
+        "kernel": "k_m2l",
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+        "traffic": None,
+        "launch_ms": round(m2l_ms, 4),
+        "pairs": int(m2l_pairs),
+        "flops_per_pair": m2l_flops_per_pair(p),
+    }
+    p2p_ms = phase_avg["p2p"]
+    p2p_tflops = p2p_pairs * p2p_flops_per_pair() / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else 0.0
+
+    line = {
+        "metric": "points/sec at 1e-6 rel err vs direct sum; served-solve p50/p99 latency",
+        "value": round(n / (ms_step * 1e-3), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "levels": L, "theta": theta, "p": p,
+                   "generator": w["gen"], "seed": w["seed"]},
+        "phase_ms": {k: round(v, 4) for k, v in phase_avg.items()},
+        "p2p": {"pairs": int(p2p_pairs), "tflops": round(p2p_tflops, 3),
+                "frac_fp64": round(p2p_tflops / FP64_PEAK_TFLOPS, 4)},
+        "roofline": roofline,
+        "wall_s": round(wall, 3),
+    }
+
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w)
+        line["accuracy"] = accuracy_gate(x, y, z, q, outs)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(w):
+    """The CPU oracle (single thread, as it stands) on a bounded sample of the
+    same workload: the same generator, theta and p with 16,384 points and 3
+    levels (the same 32 points per leaf), the full tree and upward pass, and
+    the evaluation at every point of every 8th leaf (64 of 512 leaves)."""
+    import oracle
+    ns, Ls = 16_384, 3
+    x, y, z, q, _ = workloads.workload("gmix1m", n=ns)
+    leaves = np.arange(0, 8 ** Ls, 8)
+    t0 = time.perf_counter()
+    tr = oracle.Tree(x, y, z, Ls, w["theta"])
+    tr.evaluate(q, w["p"], leaves=leaves)
+    dt = time.perf_counter() - t0
+    s = tr.start(Ls)
+    pts = int(sum(s[b + 1] - s[b] for b in leaves))
+    return {"value": round(pts / dt, 2), "unit": "points/s", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 2),
+            "sample": f"gmix generator, n={ns}, levels={Ls}, theta={w['theta']}, p={w['p']}; full tree + upward "
+                      f"pass, evaluation at the {pts} points of {len(leaves)} of {8 ** Ls} leaves"}
+
+
+def accuracy_gate(x, y, z, q, outs):
+    """Relative error of the GPU result vs the direct sum (eq. 2.1, computed
+    by the oracle) on 1,000 sampled targets."""
+    import oracle
+    tg = workloads.sample_targets(x.shape[0], 1000, seed=1)
+    d = oracle.direct(x, y, z, q, targets=tg)
+    g = [o.cpu().numpy()[tg] for o in outs]
+    ephi = float(np.linalg.norm(g[0] - d[0]) / np.linalg.norm(d[0]))
+    eE = float(np.linalg.norm(np.concatenate(g[1:]) - np.concatenate(d[1:])) / np.linalg.norm(np.concatenate(d[1:])))
+    return {"targets": 1000, "rel_err_phi": ephi, "rel_err_E": eE, "ok": bool(ephi <= 1e-6 and eE <= 1e-6)}
+
+
+if __name__ == "__main__":
+    main()
