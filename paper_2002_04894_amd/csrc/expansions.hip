@@ -33,6 +33,7 @@
 #include <mutex>
 
 #include "fmm_internal.h"
+#include "tile_layout.h"
 
 namespace fmm {
 
@@ -104,6 +105,12 @@ void gauss_legendre(int N, std::vector<double>& xs, std::vector<double>& ws) {
   }
 }
 
+long double f_all(int k) {
+  long double f = 1.0L;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
 // x-parity class of local index i within a degree: c_m (i = 2m-1) and s_m
 // (i = 2m) are even under x -> -x iff m + [s] is even.
 int parity_class(int i) {
@@ -113,30 +120,29 @@ int parity_class(int i) {
 }
 
 struct HostTables {
-  std::vector<double> J, A, B, rc;
-  std::vector<int> joff;
+  std::vector<double> J, A, B, rc, mtab;
+  std::vector<int> joff, pos, ipos;
+  int stride = 0;
+  bool tiled = false;
 };
 
-HostTables make_host_tables(int p) {
-  HostTables h;
-  // J: R_b(K v) = sum_b' J_bb' R_b'(v), K = quarter turn about x: (x,y,z) -> (x, z, -y)
-  h.joff.resize(p + 2);
-  h.joff[0] = 0;
-  for (int n = 0; n <= p; ++n) h.joff[n + 1] = h.joff[n] + (2 * n + 1) * (2 * n + 1);
-  h.J.assign(h.joff[p + 1], 0.0);
+// Rotation matrices by exact quadrature: J^n_{bb'} with
+// R_b(K v) = sum_b' J^n_{bb'} R_b'(v) for a fixed rotation K (kv = K v).
+std::vector<double> quarter_turn(int p, const std::vector<int>& joff, void (*K)(const double*, double*)) {
   const int nth = p + 2, nph = 2 * p + 2;
   std::vector<double> gx, gw;
   gauss_legendre(nth, gx, gw);
   const int nt = nterms(p);
   std::vector<double> Rv(nt), RK(nt);
-  std::vector<long double> acc(h.joff[p + 1], 0.0L);
+  std::vector<long double> acc(joff[p + 1], 0.0L);
   for (int a = 0; a < nth; ++a) {
     const double ct = gx[a];
     const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
     for (int k = 0; k < nph; ++k) {
       const double ph = 2.0 * M_PI * k / nph;
       const double v[3] = {st * cos(ph), st * sin(ph), ct};
-      const double kv[3] = {v[0], v[2], -v[1]};
+      double kv[3];
+      K(v, kv);
       host_R(p, v, Rv.data());
       host_R(p, kv, RK.data());
       const long double w = (long double)gw[a] * (2.0L * M_PI / nph);
@@ -144,17 +150,42 @@ HostTables make_host_tables(int p) {
         const int s = 2 * n + 1;
         for (int i = 0; i < s; ++i)
           for (int j = 0; j < s; ++j)
-            acc[h.joff[n] + i * s + j] += w * (long double)RK[n * n + i] * (long double)Rv[n * n + j];
+            acc[joff[n] + i * s + j] += w * (long double)RK[n * n + i] * (long double)Rv[n * n + j];
       }
     }
   }
+  std::vector<double> J(joff[p + 1]);
+  for (int n = 0; n <= p; ++n) {
+    const int s = 2 * n + 1;
+    for (int i = 0; i < s * s; ++i) J[joff[n] + i] = (double)(acc[joff[n] + i] * (2.0L * n + 1.0L) / (4.0L * M_PI));
+  }
+  return J;
+}
+
+void quarter_x(const double* v, double* kv) {  // quarter turn about x: (x, y, z) -> (x, z, -y)
+  kv[0] = v[0];
+  kv[1] = v[2];
+  kv[2] = -v[1];
+}
+void quarter_y(const double* v, double* kv) {  // quarter turn about y: (x, y, z) -> (z, y, -x)
+  kv[0] = v[2];
+  kv[1] = v[1];
+  kv[2] = -v[0];
+}
+
+HostTables make_host_tables(int p) {
+  HostTables h;
+  // J: R_b(K v) = sum_b' J_bb' R_b'(v), K = quarter turn about x: (x,y,z) -> (x, z, -y);
+  // entries between the two x-parity classes vanish and are set to 0
+  h.joff.resize(p + 2);
+  h.joff[0] = 0;
+  for (int n = 0; n <= p; ++n) h.joff[n + 1] = h.joff[n] + (2 * n + 1) * (2 * n + 1);
+  h.J = quarter_turn(p, h.joff, quarter_x);
   for (int n = 0; n <= p; ++n) {
     const int s = 2 * n + 1;
     for (int i = 0; i < s; ++i)
-      for (int j = 0; j < s; ++j) {
-        const long double v = acc[h.joff[n] + i * s + j] * (2.0L * n + 1.0L) / (4.0L * M_PI);
-        h.J[h.joff[n] + i * s + j] = parity_class(i) == parity_class(j) ? (double)v : 0.0;
-      }
+      for (int j = 0; j < s; ++j)
+        if (parity_class(i) != parity_class(j)) h.J[h.joff[n] + i * s + j] = 0.0;
   }
   // factorials
   std::vector<long double> f(2 * p + 2);
@@ -182,6 +213,44 @@ HostTables make_host_tables(int p) {
       h.rc[2 * P1 + n * P1 + m] = (2.0 * n - 1.0) / d;
       h.rc[2 * P1 + P1 * P1 + n * P1 + m] = sqrt((double)(n + m - 1) * (n - m - 1)) / d;
     }
+  // storage layout
+  const int nt = nterms(p);
+  h.tiled = p <= tl::kMaxP;
+  h.stride = h.tiled ? tl::stride(p) : nt;
+  h.pos.assign(nt, -1);
+  h.ipos.assign(h.stride, -1);
+  if (!h.tiled) {
+    for (int k = 0; k < nt; ++k) h.pos[k] = h.ipos[k] = k;
+    return h;
+  }
+  for (int t = 0; t < tl::ntiles(p); ++t)
+    for (int sl = 0; sl < 16; ++sl) {
+      const tl::Slot d = tl::decode(p, t, sl);
+      if (!d.valid) continue;
+      const int k = d.n * d.n + (d.m == 0 ? 0 : 2 * d.m - 1 + d.sine);
+      h.pos[k] = tl::spos(t, sl);
+      h.ipos[tl::spos(t, sl)] = k;
+    }
+  // MFMA tables: tile matrices of the quarter turn about y (its cosine and sine
+  // blocks; cross entries vanish), factorials, 1/sqrt((n+m)!(n-m)!)
+  const std::vector<double> Jy = quarter_turn(p, h.joff, quarter_y);
+  const int T = tl::ntiles(p);
+  h.mtab.assign((size_t)T * 16 * 17 + 32 + 256, 0.0);
+  for (int t = 0; t < T; ++t)
+    for (int r = 0; r < 16; ++r)
+      for (int c = 0; c < 16; ++c) {
+        const tl::Slot a = tl::decode(p, t, r), b = tl::decode(p, t, c);
+        if (!a.valid || !b.valid || a.n != b.n || a.sine != b.sine) continue;
+        const int n = a.n, sdim = 2 * n + 1;
+        const int ia = a.m == 0 ? 0 : 2 * a.m - 1 + a.sine;
+        const int ib = b.m == 0 ? 0 : 2 * b.m - 1 + b.sine;
+        h.mtab[(size_t)t * 272 + r * 17 + c] = Jy[h.joff[n] + ia * sdim + ib];
+      }
+  double* fct = h.mtab.data() + (size_t)T * 272;
+  for (int i = 0; i < 32; ++i) fct[i] = (double)f_all(i);
+  double* uz = fct + 32;
+  for (int m = 0; m <= p; ++m)
+    for (int n = m; n <= p; ++n) uz[16 * m + n] = (double)(1.0L / sqrtl(f_all(n + m) * f_all(n - m)));
   return h;
 }
 
@@ -213,6 +282,11 @@ const Tables& tables_for(int p, hipStream_t) {
   t.A = upload(h.A);
   t.B = upload(h.B);
   t.rc = upload(h.rc);
+  t.stride = h.stride;
+  t.pos = upload(h.pos);
+  t.ipos = upload(h.ipos);
+  t.tiled = h.tiled;
+  if (h.tiled) t.mtab = upload(h.mtab);
   return g_tabs.emplace(std::make_pair(dev, p), t).first->second;
 }
 
@@ -226,6 +300,9 @@ constexpr int kNtMax = (kMaxOrder + 1) * (kMaxOrder + 1);
 struct XT {
   int p;
   int nt;
+  int stride;
+  const int* __restrict__ pos;
+  const int* __restrict__ ipos;
   const double* __restrict__ J;
   const int* __restrict__ joff;
   const double* __restrict__ A;
@@ -233,7 +310,7 @@ struct XT {
   const double* __restrict__ rc;
 };
 
-XT make_xt(const Tables& t) { return XT{t.p, nterms(t.p), t.J, t.joff, t.A, t.B, t.rc}; }
+XT make_xt(const Tables& t) { return XT{t.p, nterms(t.p), t.stride, t.pos, t.ipos, t.J, t.joff, t.A, t.B, t.rc}; }
 
 enum Kind { kM2M = 0, kM2L = 1, kL2L = 2 };
 
@@ -387,6 +464,17 @@ __device__ void translate(int kind, double dx, double dy, double dz, double* X, 
   __syncthreads();
 }
 
+// coefficient vector (standard order, LDS) <-> storage layout (global)
+__device__ __forceinline__ void load_coefs(const double* __restrict__ src, double* dst, const XT& tb) {
+  for (int k = threadIdx.x & 63; k < tb.nt; k += 64) dst[k] = src[tb.pos[k]];
+}
+__device__ __forceinline__ void store_coefs(const double* src, double* __restrict__ dst, const XT& tb) {
+  for (int q = threadIdx.x & 63; q < tb.stride; q += 64) {
+    const int k = tb.ipos[q];
+    dst[q] = k >= 0 ? src[k] : 0.0;
+  }
+}
+
 __device__ __forceinline__ int level_of(const LevelView& lv, int64_t gid) {
   int l = 0;
   while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
@@ -410,14 +498,12 @@ __global__ __launch_bounds__(64) void k_m2l(LevelView lv, XT tb, const double* _
   for (int64_t e = e0; e < e1; ++e) {
     const int64_t j = lv.w_idx[l][e];
     const double* gj = lv.geom[l] + j * 10;
-    const double* src = Mx + (size_t)(lv.gofs[l] + j) * nt;
-    for (int k = lane; k < nt; k += 64) X[k] = src[k];
+    load_coefs(Mx + (size_t)(lv.gofs[l] + j) * tb.stride, X, tb);
     __syncthreads();
     translate(kM2L, gj[6] - cix, gj[7] - ciy, gj[8] - ciz, X, T, acc, tb, sc);
   }
   __syncthreads();
-  double* dst = Lx + (size_t)gid * nt;
-  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+  store_coefs(acc, Lx + (size_t)gid * tb.stride, tb);
 }
 
 // ---- M2M: parents of level l-1 from their 8 children on level l ----
@@ -432,14 +518,12 @@ __global__ __launch_bounds__(64) void k_m2m(LevelView lv, int l, XT tb, double* 
   for (int c = 0; c < 8; ++c) {
     const int64_t ch = 8 * par + c;
     const double* gc = lv.geom[l] + ch * 10;
-    const double* src = Mx + (size_t)(lv.gofs[l] + ch) * nt;
-    for (int k = lane; k < nt; k += 64) X[k] = src[k];
+    load_coefs(Mx + (size_t)(lv.gofs[l] + ch) * tb.stride, X, tb);
     __syncthreads();
     translate(kM2M, gc[6] - gp[6], gc[7] - gp[7], gc[8] - gp[8], X, T, acc, tb, sc);
   }
   __syncthreads();
-  double* dst = Mx + (size_t)(lv.gofs[l - 1] + par) * nt;
-  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+  store_coefs(acc, Mx + (size_t)(lv.gofs[l - 1] + par) * tb.stride, tb);
 }
 
 // ---- L2L: children of level l receive their parent's local expansion ----
@@ -452,15 +536,12 @@ __global__ __launch_bounds__(64) void k_l2l(LevelView lv, int l, XT tb, double* 
   const int64_t par = ch >> 3;
   const double* gc = lv.geom[l] + ch * 10;
   const double* gp = lv.geom[l - 1] + par * 10;
-  double* dst = Lx + (size_t)(lv.gofs[l] + ch) * nt;
-  const double* src = Lx + (size_t)(lv.gofs[l - 1] + par) * nt;
-  for (int k = lane; k < nt; k += 64) {
-    acc[k] = dst[k];
-    X[k] = src[k];
-  }
+  double* dst = Lx + (size_t)(lv.gofs[l] + ch) * tb.stride;
+  load_coefs(dst, acc, tb);
+  load_coefs(Lx + (size_t)(lv.gofs[l - 1] + par) * tb.stride, X, tb);
   __syncthreads();
   translate(kL2L, gc[6] - gp[6], gc[7] - gp[7], gc[8] - gp[8], X, T, acc, tb, sc);
-  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+  store_coefs(acc, dst, tb);
 }
 
 // ---- P2M: one 64-lane workgroup per leaf, lanes over points ----
@@ -531,8 +612,7 @@ __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* _
     }
   }
   __syncthreads();
-  double* dst = Mx + (size_t)(lv.gofs[L] + b) * nt;
-  for (int k = lane; k < nt; k += 64) dst[k] = acc[k];
+  store_coefs(acc, Mx + (size_t)(lv.gofs[L] + b) * tb.stride, tb);
 }
 
 // ---- L2P: far field at the points of each leaf (phi and E = -grad phi) ----
@@ -547,7 +627,8 @@ __global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const double* _
   const double* g = lv.geom[L] + b * 10;
   const double cx = g[6], cy = g[7], cz = g[8];
   const int s0 = lv.start[L][b], s1 = lv.start[L][b + 1];
-  const double* Lc = Lx + (size_t)(lv.gofs[L] + b) * nt;
+  const double* Lc = Lx + (size_t)(lv.gofs[L] + b) * tb.stride;
+  const int* pos = tb.pos;
   const double* am = tb.rc;
   const double* bm = tb.rc + P1;
   const double* c1 = tb.rc + 2 * P1;
@@ -600,8 +681,8 @@ __global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const double* _
             g1[u] = gn[u];
           }
         }
-        const double lc = Lc[cidx(n, m, 0)] * (m == 0 ? 1.0 : s2);
-        const double ls = m == 0 ? 0.0 : Lc[cidx(n, m, 1)] * s2;
+        const double lc = Lc[pos[cidx(n, m, 0)]] * (m == 0 ? 1.0 : s2);
+        const double ls = m == 0 ? 0.0 : Lc[pos[cidx(n, m, 1)]] * s2;
         f += lc * gn[0] + ls * gn[1];
         fx += lc * gn[2] + ls * gn[3];
         fy += lc * gn[4] + ls * gn[5];
@@ -626,7 +707,10 @@ void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t 
   k_m2m<<<(unsigned)t.lev[l - 1].nbox, 64, 0, s>>>(t.view(), l, make_xt(tb), Mx);
   HIPCHECK(hipGetLastError());
 }
+bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
+
 void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
+  if (launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
   const int64_t nb = t.nbox_total - 1;  // levels 1..L
   k_m2l<<<(unsigned)nb, 64, 0, s>>>(t.view(), make_xt(tb), Mx, Lx);
   HIPCHECK(hipGetLastError());

@@ -82,6 +82,16 @@ struct Tables {
   double* A = nullptr;     // M2L along z: A[(m*(p+1) + j)*(p+1) + n]
   double* B = nullptr;     // M2M / L2L along z: B[(m*(p+1) + n)*(p+1) + j]
   double* rc = nullptr;    // recurrence constants, see expansions.hip
+  // storage of one expansion: `stride` doubles per box; coefficient k
+  // (k = n^2, n^2+2m-1, n^2+2m for c_{n,0}, c_{n,m}, s_{n,m}) lives at pos[k];
+  // ipos[q] is the coefficient at storage position q, or -1 for a zero slot
+  int stride = 0;
+  int* pos = nullptr;
+  int* ipos = nullptr;
+  // MFMA translation tables (p <= 15): y-quarter-turn tile matrices
+  // [ntiles][16][17], factorials [32], 1/sqrt((n+m)!(n-m)!) at [16*m + n]
+  double* mtab = nullptr;
+  bool tiled = false;
 };
 const Tables& tables_for(int p, hipStream_t s);
 

@@ -102,9 +102,8 @@ void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, dou
   const bool do_far = (parts & FMM_PART_FAR) && L >= 1;
   if (do_far) {
     const Tables& tb = tables_for(p, s);
-    const int nt = nterms(p);
-    double* Mx = (double*)dalloc((size_t)t.nbox_total * nt * sizeof(double), s);
-    double* Lx = (double*)dalloc((size_t)t.nbox_total * nt * sizeof(double), s);
+    double* Mx = (double*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(double), s);
+    double* Lx = (double*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(double), s);
     for (int k = 0; k < 4; ++k) far[k] = (double*)dalloc(n * sizeof(double), s);
     tm.begin(FMM_PH_P2M, s);
     launch_p2m(t, tb, qt, Mx, s);
