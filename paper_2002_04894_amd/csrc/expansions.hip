@@ -530,8 +530,6 @@ __global__ __launch_bounds__(64) void k_m2m(LevelView lv, int l, XT tb, double* 
 __global__ __launch_bounds__(64) void k_l2l(LevelView lv, int l, XT tb, double* __restrict__ Lx) {
   __shared__ double X[kNtMax], T[kNtMax], acc[kNtMax];
   __shared__ XScratch sc;
-  const int lane = threadIdx.x;
-  const int nt = tb.nt;
   const int64_t ch = blockIdx.x;
   const int64_t par = ch >> 3;
   const double* gc = lv.geom[l] + ch * 10;
@@ -622,7 +620,7 @@ __global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const double* _
                                             double* __restrict__ fex, double* __restrict__ fey,
                                             double* __restrict__ fez) {
   const int lane = threadIdx.x;
-  const int L = lv.L, p = tb.p, P1 = p + 1, nt = tb.nt;
+  const int L = lv.L, p = tb.p, P1 = p + 1;
   const int64_t b = blockIdx.x;
   const double* g = lv.geom[L] + b * 10;
   const double cx = g[6], cy = g[7], cz = g[8];
