@@ -59,6 +59,8 @@ void release(Tree& t) {
   f(t.py);
   f(t.pz);
   f(t.perm);
+  f(t.m2l_order);
+  t.m2l_order = nullptr;
   for (Level& V : t.lev) {
     f(V.geom);
     f(V.start);

@@ -69,6 +69,7 @@ struct Tree {
   int32_t* perm = nullptr;
   std::vector<Level> lev;     // 0..L
   int64_t nbox_total = 0;     // sum over levels 0..L
+  int32_t* m2l_order = nullptr;  // M2L targets (box id - 1), longest weak list first
   int64_t m2l_pairs = 0;
   int64_t p2p_pairs = 0;
   LevelView view() const;

@@ -6,6 +6,9 @@
 // (R, r the larger and smaller radius), otherwise strongly connected.  The
 // lists are CSR by target box: a count pass, a scan, and a fill pass (the
 // same loop writing indices), so each row comes out in ascending order.
+#include <algorithm>
+#include <numeric>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -213,6 +216,27 @@ void lists_build(Tree& t, hipStream_t s) {
   }
   HIPCHECK(hipHostFree(tot));
   t.m2l_pairs = m2l;
+
+  // M2L work order: targets of levels 1..L by decreasing weak-list length
+  // (ties by box id), so that long lists start first and the tail is short
+  const int64_t ntarget = t.nbox_total - 1;
+  if (ntarget > 0) {
+    std::vector<int64_t> cnt(ntarget);
+    std::vector<int64_t> off;
+    for (int l = 1; l <= L; ++l) {
+      const Level& V = t.lev[l];
+      off.resize(V.nbox + 1);
+      HIPCHECK(hipMemcpyAsync(off.data(), V.w_off, (V.nbox + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int64_t i = 0; i < V.nbox; ++i) cnt[V.gofs - 1 + i] = off[i + 1] - off[i];
+    }
+    std::vector<int32_t> ord(ntarget);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+    t.m2l_order = (int32_t*)dalloc(ntarget * sizeof(int32_t), s);
+    HIPCHECK(hipMemcpyAsync(t.m2l_order, ord.data(), ntarget * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));  // ord is a host temporary
+  }
 }
 
 void tree_compute_stats(Tree& t, hipStream_t s) {

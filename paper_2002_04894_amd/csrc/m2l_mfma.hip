@@ -204,7 +204,8 @@ __device__ __forceinline__ void ztrans_part(d4* st, double* zb, const double* fc
 template <int P>
 __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double* __restrict__ mtab,
                                                      const double* __restrict__ Mx, double* __restrict__ Lx,
-                                                     int64_t ntarget) {
+                                                     int64_t ntarget, const int32_t* __restrict__ order,
+                                                     int* __restrict__ queue) {
   using C = Cfg<P>;
   constexpr int T = C::T;
   constexpr int S = C::S;
@@ -218,111 +219,130 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
   for (int k = threadIdx.x; k < C::SHARED; k += 256) smem[k] = mtab[k];
   __syncthreads();
 
-  const int64_t tgt = (int64_t)blockIdx.x * 4 + wid;
-  if (tgt >= ntarget) return;  // no block-wide barrier below this point
-  const int64_t gid = lv.gofs[1] + tgt;
-  const int l = level_of2(lv, gid);
-  const int64_t bi = gid - lv.gofs[l];
-  const int r16 = lane & 15, g = lane >> 4;
-  const double* geo = lv.geom[l];
-  const double cix = geo[bi * 10 + 6], ciy = geo[bi * 10 + 7], ciz = geo[bi * 10 + 8];
-  const int64_t e0 = lv.w_off[l][bi], e1 = lv.w_off[l][bi + 1];
-  const int32_t* widx = lv.w_idx[l];
-  const double* Mlev = Mx + (size_t)lv.gofs[l] * S;
-  double* tp = trig + r16 * C::TRIG;  // this lane's pair
-  const double* cs_a = tp;
-  const double* cs_t = tp + 2 * (P + 1);
-  const double* rp = tp + 4 * (P + 1);
+  // persistent waves: each takes the next target of the longest-first order
+  // until the queue is empty (no block-wide barrier below this point)
+  for (;;) {
+    int k_next = 0;
+    if (lane == 0) k_next = atomicAdd(queue, 1);
+    k_next = __shfl(k_next, 0);
+    if (k_next >= ntarget) break;
+    const int64_t tgt = order[k_next];
+    const int64_t gid = lv.gofs[1] + tgt;
+    const int l = level_of2(lv, gid);
+    const int64_t bi = gid - lv.gofs[l];
+    const int r16 = lane & 15, g = lane >> 4;
+    const double* geo = lv.geom[l];
+    const double cix = geo[bi * 10 + 6], ciy = geo[bi * 10 + 7], ciz = geo[bi * 10 + 8];
+    const int64_t e0 = lv.w_off[l][bi], e1 = lv.w_off[l][bi + 1];
+    const int32_t* widx = lv.w_idx[l];
+    const double* Mlev = Mx + (size_t)lv.gofs[l] * S;
+    double* tp = trig + r16 * C::TRIG;  // this lane's pair
+    const double* cs_a = tp;
+    const double* cs_t = tp + 2 * (P + 1);
+    const double* rp = tp + 4 * (P + 1);
 
-  // compact accumulator: lane r16 owns the tiles t with t % 16 == r16
-  constexpr int NA = (T + 15) / 16;
-  d4 acc[NA];
+    // compact accumulator: lane r16 owns the tiles t with t % 16 == r16
+    constexpr int NA = (T + 15) / 16;
+    d4 acc[NA];
 #pragma unroll
-  for (int k = 0; k < NA; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < NA; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t eb = e0; eb < e1; eb += 16) {
-    const int64_t e = eb + r16;
-    const bool valid = e < e1;
-    const int j = widx[valid ? e : e0];
-    double dx = geo[(int64_t)j * 10 + 6] - cix, dy = geo[(int64_t)j * 10 + 7] - ciy,
-           dz = geo[(int64_t)j * 10 + 8] - ciz;
-    if (!valid) {
-      dx = 0.0;
-      dy = 0.0;
-      dz = 1.0;
-    }
-    const double rxy2 = dx * dx + dy * dy;
-    const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
-    // trig and power tables of this pair, split over the 4 lanes of the pair
-    if (g == 0) {
-      const double ca = dz / rho, sa = rxy / rho;
-      double c = 1.0, s = 0.0;
-      for (int m = 0; m <= P; ++m) {
-        tp[2 * m] = c;
-        tp[2 * m + 1] = s;
-        const double nc = c * ca - s * sa, ns = s * ca + c * sa;
-        c = nc;
-        s = ns;
+    for (int64_t eb = e0; eb < e1; eb += 16) {
+      const int64_t e = eb + r16;
+      const bool valid = e < e1;
+      const int j = widx[valid ? e : e0];
+      double dx = geo[(int64_t)j * 10 + 6] - cix, dy = geo[(int64_t)j * 10 + 7] - ciy,
+             dz = geo[(int64_t)j * 10 + 8] - ciz;
+      if (!valid) {
+        dx = 0.0;
+        dy = 0.0;
+        dz = 1.0;
       }
-    } else if (g == 1) {
-      // theta2 = pi/2 - beta: cos = sin(beta), sin = cos(beta)
-      const double ct = rxy > 0.0 ? dy / rxy : 0.0, st2 = rxy > 0.0 ? dx / rxy : 1.0;
-      double c = 1.0, s = 0.0;
-      for (int m = 0; m <= P; ++m) {
-        tp[2 * (P + 1) + 2 * m] = c;
-        tp[2 * (P + 1) + 2 * m + 1] = s;
-        const double nc = c * ct - s * st2, ns = s * ct + c * st2;
-        c = nc;
-        s = ns;
+      const double rxy2 = dx * dx + dy * dy;
+      const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
+      // trig and power tables of this pair, split over the 4 lanes of the pair
+      if (g == 0) {
+        const double ca = dz / rho, sa = rxy / rho;
+        double c = 1.0, s = 0.0;
+        for (int m = 0; m <= P; ++m) {
+          tp[2 * m] = c;
+          tp[2 * m + 1] = s;
+          const double nc = c * ca - s * sa, ns = s * ca + c * sa;
+          c = nc;
+          s = ns;
+        }
+      } else if (g == 1) {
+        // theta2 = pi/2 - beta: cos = sin(beta), sin = cos(beta)
+        const double ct = rxy > 0.0 ? dy / rxy : 0.0, st2 = rxy > 0.0 ? dx / rxy : 1.0;
+        double c = 1.0, s = 0.0;
+        for (int m = 0; m <= P; ++m) {
+          tp[2 * (P + 1) + 2 * m] = c;
+          tp[2 * (P + 1) + 2 * m + 1] = s;
+          const double nc = c * ct - s * st2, ns = s * ct + c * st2;
+          c = nc;
+          s = ns;
+        }
+      } else if (g == 2) {
+        const double ir = 1.0 / rho;
+        double v = 1.0;
+        for (int k = 0; k <= P + 1; ++k) {
+          tp[4 * (P + 1) + k] = v;
+          v *= ir;
+        }
       }
-    } else if (g == 2) {
-      const double ir = 1.0 / rho;
-      double v = 1.0;
-      for (int k = 0; k <= P + 1; ++k) {
-        tp[4 * (P + 1) + k] = v;
-        v *= ir;
-      }
-    }
-    d4 st[T];
-    const double* src = Mlev + (size_t)j * S + 4 * g;
+      d4 st[T];
+      const double* src = Mlev + (size_t)j * S + 4 * g;
 #pragma unroll
-    for (int t = 0; t < T; ++t) st[t] = valid ? *(const d4*)(src + 16 * t) : d4{0.0, 0.0, 0.0, 0.0};
-    wave_lds_sync();
+      for (int t = 0; t < T; ++t) st[t] = valid ? *(const d4*)(src + 16 * t) : d4{0.0, 0.0, 0.0, 0.0};
+      wave_lds_sync();
 
-    rotz<P>(st, cs_t, 1.0, g);
-    japply<P, true>(st, Jt, r16, g);
-    rotz<P>(st, cs_a, 1.0, g);
-    japply<P, false>(st, Jt, r16, g);
-    ztrans_part<P, 0>(st, zb, fct, uz, rp, r16, g);
-    ztrans_part<P, 1>(st, zb, fct, uz, rp, r16, g);
-    japply<P, true>(st, Jt, r16, g);
-    rotz<P>(st, cs_a, -1.0, g);
-    japply<P, false>(st, Jt, r16, g);
-    rotz<P>(st, cs_t, -1.0, g);
-    // sum this batch over its 16 pairs; the owner lane of each tile keeps it
+      rotz<P>(st, cs_t, 1.0, g);
+      japply<P, true>(st, Jt, r16, g);
+      rotz<P>(st, cs_a, 1.0, g);
+      japply<P, false>(st, Jt, r16, g);
+      ztrans_part<P, 0>(st, zb, fct, uz, rp, r16, g);
+      ztrans_part<P, 1>(st, zb, fct, uz, rp, r16, g);
+      japply<P, true>(st, Jt, r16, g);
+      rotz<P>(st, cs_a, -1.0, g);
+      japply<P, false>(st, Jt, r16, g);
+      rotz<P>(st, cs_t, -1.0, g);
+      // sum this batch over its 16 pairs; the owner lane of each tile keeps it
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      d4 v;
+      for (int t = 0; t < T; ++t) {
+        d4 v;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = row_sum16(st[t][i]);
-      if (r16 == (t & 15)) acc[t >> 4] += v;
+        for (int i = 0; i < 4; ++i) v[i] = row_sum16(st[t][i]);
+        if (r16 == (t & 15)) acc[t >> 4] += v;
+      }
+      wave_lds_sync();  // trig table is rewritten by the next batch
     }
-    wave_lds_sync();  // trig table is rewritten by the next batch
-  }
-  double* dst = Lx + (size_t)gid * S + 4 * g;
+    double* dst = Lx + (size_t)gid * S + 4 * g;
 #pragma unroll
-  for (int k = 0; k < NA; ++k) {
-    const int t = 16 * k + r16;
-    if (t < T) *(d4*)(dst + 16 * t) = acc[k];
+    for (int k = 0; k < NA; ++k) {
+      const int t = 16 * k + r16;
+      if (t < T) *(d4*)(dst + 16 * t) = acc[k];
+    }
   }
 }
 
 template <int P>
 void launch_one(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   const int64_t ntarget = t.nbox_total - 1;
-  const unsigned grid = (unsigned)((ntarget + 3) / 4);
-  k_m2l_mfma<P><<<grid, 256, 0, s>>>(t.view(), tb.mtab, Mx, Lx, ntarget);
+  static int grid_max = 0;  // resident blocks of this instantiation on the device
+  if (grid_max == 0) {
+    int dev = 0, ncu = 0, per = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P>, 256, 0));
+    grid_max = ncu * (per > 0 ? per : 1);
+  }
+  const int64_t need = (ntarget + 3) / 4;
+  const unsigned grid = (unsigned)(need < grid_max ? need : grid_max);
+  int* queue = (int*)dalloc(sizeof(int), s);
+  HIPCHECK(hipMemsetAsync(queue, 0, sizeof(int), s));
+  k_m2l_mfma<P><<<grid, 256, 0, s>>>(t.view(), tb.mtab, Mx, Lx, ntarget, t.m2l_order, queue);
   HIPCHECK(hipGetLastError());
+  dfree(queue, s);
 }
 
 }  // namespace
