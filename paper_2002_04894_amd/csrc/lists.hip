@@ -7,7 +7,6 @@
 // lists are CSR by target box: a count pass, a scan, and a fill pass (the
 // same loop writing indices), so each row comes out in ascending order.
 #include <algorithm>
-#include <numeric>
 
 #include "fmm_internal.h"
 
@@ -25,39 +24,69 @@ __device__ __forceinline__ bool is_weak(const double* gi, const double* gj, doub
   return R + theta * r <= theta * d;
 }
 
+// One wave per target box i; lanes take 64 consecutive candidates at a time
+// and a ballot compacts them, so each row keeps ascending candidate order.
 template <bool FILL>
-__global__ void k_lists(int64_t nbox, const double* __restrict__ geom, const int64_t* __restrict__ ps_off,
-                        const int32_t* __restrict__ ps_idx, double theta, int32_t* __restrict__ ns,
-                        int32_t* __restrict__ nw, const int64_t* __restrict__ s_off, int32_t* __restrict__ s_idx,
-                        const int64_t* __restrict__ w_off, int32_t* __restrict__ w_idx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_lists(int64_t nbox, const double* __restrict__ geom,
+                                               const int64_t* __restrict__ ps_off, const int32_t* __restrict__ ps_idx,
+                                               double theta, int32_t* __restrict__ ns, int32_t* __restrict__ nw,
+                                               const int64_t* __restrict__ s_off, int32_t* __restrict__ s_idx,
+                                               const int64_t* __restrict__ w_off, int32_t* __restrict__ w_idx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= nbox) return;
   const int64_t par = i >> 3;
   const double* gi = geom + i * 10;
-  int cs = 0, cw = 0;
+  const int64_t e0 = ps_off[par];
+  const int64_t ncand = 8 * (ps_off[par + 1] - e0);
+  const uint64_t below = (1ull << lane) - 1ull;
   int64_t so = 0, wo = 0;
   if (FILL) {
     so = s_off[i];
     wo = w_off[i];
   }
-  for (int64_t e = ps_off[par]; e < ps_off[par + 1]; ++e) {
-    const int64_t J = ps_idx[e];
-    for (int c = 0; c < 8; ++c) {
-      const int64_t j = 8 * J + c;
-      const bool weak = (j != i) && is_weak(gi, geom + j * 10, theta);
-      if (weak) {
-        if (FILL) w_idx[wo + cw] = (int32_t)j;
-        ++cw;
-      } else {
-        if (FILL) s_idx[so + cs] = (int32_t)j;
-        ++cs;
-      }
+  int64_t cs = 0, cw = 0;
+  for (int64_t k0 = 0; k0 < ncand; k0 += 64) {
+    const int64_t k = k0 + lane;
+    const bool valid = k < ncand;
+    const int64_t j = valid ? 8 * (int64_t)ps_idx[e0 + (k >> 3)] + (k & 7) : 0;
+    const bool weak = valid && (j != i) && is_weak(gi, geom + j * 10, theta);
+    const bool strong = valid && !weak;
+    const uint64_t mw = __ballot(weak), ms = __ballot(strong);
+    if (FILL) {
+      if (weak) w_idx[wo + cw + __popcll(mw & below)] = (int32_t)j;
+      if (strong) s_idx[so + cs + __popcll(ms & below)] = (int32_t)j;
     }
+    cw += __popcll(mw);
+    cs += __popcll(ms);
   }
-  if (!FILL) {
-    ns[i] = cs;
-    nw[i] = cw;
+  if (!FILL && lane == 0) {
+    ns[i] = (int32_t)cs;
+    nw[i] = (int32_t)cw;
   }
+}
+
+// M2L work order, longest weak list first: targets are binned by list length
+// (bin 0 = longest), the bins scanned, then scattered.  The order within a
+// bin is not fixed; it only schedules work, every target's result is the same.
+constexpr int kOrderBins = 4096;
+
+__global__ void k_order_hist(int64_t nbox, const int64_t* __restrict__ w_off,
+                             int32_t* __restrict__ hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbox) return;
+  const int64_t c = w_off[i + 1] - w_off[i];
+  atomicAdd(&hist[kOrderBins - 1 - (int)(c < kOrderBins - 1 ? c : kOrderBins - 1)], 1);
+}
+
+__global__ void k_order_scatter(int64_t nbox, int64_t gofs, const int64_t* __restrict__ w_off,
+                                unsigned long long* __restrict__ cursor, int32_t* __restrict__ order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbox) return;
+  const int64_t c = w_off[i + 1] - w_off[i];
+  const int b = kOrderBins - 1 - (int)(c < kOrderBins - 1 ? c : kOrderBins - 1);
+  const unsigned long long pos = atomicAdd(&cursor[b], 1ull);
+  order[pos] = (int32_t)(gofs - 1 + i);
 }
 
 // ---- exclusive scan: per-block scan, scan of block sums, add ----
@@ -192,7 +221,7 @@ void lists_build(Tree& t, hipStream_t s) {
     const int64_t nb = V.nbox;
     int32_t* ns = (int32_t*)dalloc(nb * sizeof(int32_t), s);
     int32_t* nw = (int32_t*)dalloc(nb * sizeof(int32_t), s);
-    const unsigned grid = (unsigned)((nb + 255) / 256);
+    const unsigned grid = (unsigned)((nb + 3) / 4);
     k_lists<false><<<grid, 256, 0, s>>>(nb, V.geom, P.s_off, P.s_idx, t.theta, ns, nw, nullptr, nullptr, nullptr,
                                         nullptr);
     HIPCHECK(hipGetLastError());
@@ -217,25 +246,27 @@ void lists_build(Tree& t, hipStream_t s) {
   HIPCHECK(hipHostFree(tot));
   t.m2l_pairs = m2l;
 
-  // M2L work order: targets of levels 1..L by decreasing weak-list length
-  // (ties by box id), so that long lists start first and the tail is short
+  // M2L work order over the targets of levels 1..L (box id - 1)
   const int64_t ntarget = t.nbox_total - 1;
   if (ntarget > 0) {
-    std::vector<int64_t> cnt(ntarget);
-    std::vector<int64_t> off;
+    int32_t* hist = (int32_t*)dalloc(kOrderBins * sizeof(int32_t), s);
+    int64_t* cursor = (int64_t*)dalloc((kOrderBins + 1) * sizeof(int64_t), s);
+    HIPCHECK(hipMemsetAsync(hist, 0, kOrderBins * sizeof(int32_t), s));
     for (int l = 1; l <= L; ++l) {
       const Level& V = t.lev[l];
-      off.resize(V.nbox + 1);
-      HIPCHECK(hipMemcpyAsync(off.data(), V.w_off, (V.nbox + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
-      for (int64_t i = 0; i < V.nbox; ++i) cnt[V.gofs - 1 + i] = off[i + 1] - off[i];
+      k_order_hist<<<(unsigned)((V.nbox + 255) / 256), 256, 0, s>>>(V.nbox, V.w_off, hist);
+      HIPCHECK(hipGetLastError());
     }
-    std::vector<int32_t> ord(ntarget);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+    scan_counts(hist, cursor, kOrderBins, 0, s);
     t.m2l_order = (int32_t*)dalloc(ntarget * sizeof(int32_t), s);
-    HIPCHECK(hipMemcpyAsync(t.m2l_order, ord.data(), ntarget * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHECK(hipStreamSynchronize(s));  // ord is a host temporary
+    for (int l = 1; l <= L; ++l) {
+      const Level& V = t.lev[l];
+      k_order_scatter<<<(unsigned)((V.nbox + 255) / 256), 256, 0, s>>>(
+          V.nbox, V.gofs, V.w_off, (unsigned long long*)cursor, t.m2l_order);
+      HIPCHECK(hipGetLastError());
+    }
+    dfree(hist, s);
+    dfree(cursor, s);
   }
 }
 

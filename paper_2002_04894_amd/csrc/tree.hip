@@ -315,6 +315,298 @@ __global__ __launch_bounds__(BS) void k_orb_round(
   }
 }
 
+// ---- the same bisection round for few, large segments: every segment is
+// cut into chunks of kChunk points, one block per chunk, and the select /
+// partition steps go through per-segment state in global memory ----
+constexpr int kChunk = 2048;
+constexpr int kChunkBS = 256;
+constexpr int kSelPasses = 8;  // 8-bit digits cover the 64-bit key
+
+struct SegSel {
+  uint64_t prefix;
+  int shift;
+  int rank;
+  int cnt;
+  int axis;
+};
+
+__device__ __forceinline__ int seg_axis(const double* lo, const double* hi) {
+  int axis = 0;
+  double ext = hi[0] - lo[0];
+  if (hi[1] - lo[1] > ext) { ext = hi[1] - lo[1]; axis = 1; }
+  if (hi[2] - lo[2] > ext) { axis = 2; }
+  return axis;
+}
+
+// state of segment blockIdx.x; clears its global histogram
+__global__ __launch_bounds__(256) void k_mb_init(const double* __restrict__ cells, const int32_t* __restrict__ seg_n,
+                                                 int depth, SegSel* __restrict__ sel, unsigned* __restrict__ ghist) {
+  const int64_t seg = ((int64_t)1 << depth) - 1 + blockIdx.x;
+  ghist[(size_t)blockIdx.x * 256 + threadIdx.x] = 0u;
+  if (threadIdx.x != 0) return;
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = cells[seg * 6 + a];
+    hi[a] = cells[seg * 6 + 3 + a];
+  }
+  const int axis = seg_axis(lo, hi);
+  const uint64_t klo = okey(lo[axis]), khi = okey(hi[axis]);
+  const uint64_t dif = klo ^ khi;
+  const int sh = dif ? __clzll((long long)dif) : 64;
+  SegSel st;
+  st.shift = sh;
+  st.prefix = sh == 0 ? 0ull : (klo >> (64 - sh));
+  st.rank = seg_n[seg] / 2;
+  st.cnt = seg_n[seg];
+  st.axis = axis;
+  sel[blockIdx.x] = st;
+}
+
+// digit histogram of the keys that still match the selected prefix
+__global__ __launch_bounds__(kChunkBS) void k_mb_hist(const double* __restrict__ xin, const double* __restrict__ yin,
+                                                      const double* __restrict__ zin,
+                                                      const int32_t* __restrict__ seg_start,
+                                                      const int32_t* __restrict__ seg_n, int depth, int nchunk,
+                                                      const SegSel* __restrict__ sel, unsigned* __restrict__ ghist) {
+  __shared__ unsigned hist[256];
+  const int sg = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
+  const SegSel st = sel[sg];
+  if (st.cnt <= 1 || st.shift >= 64) return;  // selection finished
+  const int64_t seg = ((int64_t)1 << depth) - 1 + sg;
+  const int start = seg_start[seg], n = seg_n[seg];
+  const int i0 = c * kChunk, i1 = min(n, i0 + kChunk);
+  if (i0 >= i1) return;
+  const double* cin = st.axis == 0 ? xin : (st.axis == 1 ? yin : zin);
+  const int shift = st.shift;
+  const int D = min(8, 64 - shift);
+  hist[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int i = i0 + threadIdx.x; i < i1; i += kChunkBS) {
+    const uint64_t k = okey(cin[start + i]);
+    const bool match = (shift == 0) || ((k >> (64 - shift)) == st.prefix);
+    if (match) atomicAdd(&hist[(unsigned)((k << shift) >> (64 - D))], 1u);
+  }
+  __syncthreads();
+  const unsigned h = hist[threadIdx.x];
+  if (h) atomicAdd(&ghist[(size_t)sg * 256 + threadIdx.x], h);
+}
+
+// pick the digit that holds the wanted rank (one wave per segment)
+__global__ __launch_bounds__(64) void k_mb_select(SegSel* __restrict__ sel, unsigned* __restrict__ ghist) {
+  const int lane = threadIdx.x;
+  SegSel st = sel[blockIdx.x];
+  if (st.cnt <= 1 || st.shift >= 64) return;
+  const int D = min(8, 64 - st.shift);
+  unsigned* hg = ghist + (size_t)blockIdx.x * 256;
+  unsigned h[4];
+  unsigned s = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    h[q] = hg[lane * 4 + q];
+    s += h[q];
+    hg[lane * 4 + q] = 0u;
+  }
+  unsigned inc = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned t = __shfl_up(inc, d);
+    if (lane >= d) inc += t;
+  }
+  const unsigned exc = inc - s;
+  const unsigned r = (unsigned)st.rank;
+  if (s > 0 && exc <= r && r < inc) {
+    unsigned before = exc;
+    int q = 0;
+    while (before + h[q] <= r) {
+      before += h[q];
+      ++q;
+    }
+    st.prefix = (st.prefix << D) | (uint64_t)(lane * 4 + q);
+    st.shift = st.shift + D;
+    st.rank = (int)(r - before);
+    st.cnt = (int)h[q];
+    sel[blockIdx.x] = st;
+  }
+}
+
+__device__ __forceinline__ void mb_flags(const SegSel& st, double c, bool& less, bool& match) {
+  const uint64_t top = okey(c) >> (64 - st.shift);  // shift >= 1 once a pass has run
+  less = top < st.prefix;
+  match = top == st.prefix;
+}
+
+// per chunk: points below the selected prefix, and points matching it
+__global__ __launch_bounds__(kChunkBS) void k_mb_count(const double* __restrict__ xin, const double* __restrict__ yin,
+                                                       const double* __restrict__ zin,
+                                                       const int32_t* __restrict__ seg_start,
+                                                       const int32_t* __restrict__ seg_n, int depth, int nchunk,
+                                                       const SegSel* __restrict__ sel, int2* __restrict__ ccount) {
+  __shared__ int sm[kChunkBS / 64][2];
+  const int sg = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
+  const SegSel st = sel[sg];
+  const int64_t seg = ((int64_t)1 << depth) - 1 + sg;
+  const int start = seg_start[seg], n = seg_n[seg];
+  const int i0 = c * kChunk, i1 = min(n, i0 + kChunk);
+  const double* cin = st.axis == 0 ? xin : (st.axis == 1 ? yin : zin);
+  int nl = 0, ne = 0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kChunkBS) {
+    bool less, match;
+    mb_flags(st, cin[start + i], less, match);
+    nl += less;
+    ne += match;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    nl += __shfl_xor(nl, d);
+    ne += __shfl_xor(ne, d);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sm[wid][0] = nl;
+    sm[wid][1] = ne;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0, b = 0;
+    for (int w = 0; w < kChunkBS / 64; ++w) {
+      a += sm[w][0];
+      b += sm[w][1];
+    }
+    ccount[blockIdx.x] = make_int2(a, b);
+  }
+}
+
+// per segment: where each chunk's low and equal points start (one wave)
+__global__ __launch_bounds__(64) void k_mb_scan(const SegSel* __restrict__ sel, int nchunk,
+                                                const int2* __restrict__ ccount, int2* __restrict__ cbase) {
+  const int lane = threadIdx.x;
+  const int rank = sel[blockIdx.x].rank;
+  int low_base = 0, eq_base = 0;
+  for (int c0 = 0; c0 < nchunk; c0 += 64) {
+    const int c = c0 + lane;
+    const int2 v = c < nchunk ? ccount[(size_t)blockIdx.x * nchunk + c] : make_int2(0, 0);
+    int e = v.y;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(e, d);
+      if (lane >= d) e += t;
+    }
+    const int eq_exc = eq_base + e - v.y;
+    const int take = min(v.y, max(0, rank - eq_exc));  // equal points of this chunk on the low side
+    const int lowc = v.x + take;
+    int lw = lowc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(lw, d);
+      if (lane >= d) lw += t;
+    }
+    if (c < nchunk) cbase[(size_t)blockIdx.x * nchunk + c] = make_int2(low_base + lw - lowc, eq_exc);
+    low_base += __shfl(lw, 63);
+    eq_base += __shfl(e, 63);
+  }
+}
+
+// stable scatter of one chunk; partial max of the low and min of the high side
+__global__ __launch_bounds__(kChunkBS) void k_mb_scatter(
+    const double* __restrict__ xin, const double* __restrict__ yin, const double* __restrict__ zin,
+    const int32_t* __restrict__ iin, double* __restrict__ xout, double* __restrict__ yout, double* __restrict__ zout,
+    int32_t* __restrict__ iout, const int32_t* __restrict__ seg_start, const int32_t* __restrict__ seg_n, int depth,
+    int nchunk, const SegSel* __restrict__ sel, const int2* __restrict__ cbase, double2* __restrict__ cpart) {
+  __shared__ int scan_sm[kChunkBS / 64 + 1];
+  __shared__ double red_sm[kChunkBS / 64 + 1];
+  const int sg = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
+  const SegSel st = sel[sg];
+  const int64_t seg = ((int64_t)1 << depth) - 1 + sg;
+  const int start = seg_start[seg], n = seg_n[seg];
+  const int m = n / 2;
+  const int i0 = c * kChunk, i1 = min(n, i0 + kChunk);
+  const int2 bs = cbase[blockIdx.x];
+  int low_base = bs.x, eq_base = bs.y;
+  double cmax_low = -INFINITY, cmin_high = INFINITY;
+  for (int c0 = i0; c0 < i1; c0 += kChunkBS) {  // block-uniform trip count
+    const int i = c0 + threadIdx.x;
+    const bool valid = i < i1;
+    double cx = 0, cy = 0, cz = 0, cc = 0;
+    int id = 0;
+    bool less = false, match = false;
+    if (valid) {
+      cx = xin[start + i];
+      cy = yin[start + i];
+      cz = zin[start + i];
+      id = iin[start + i];
+      cc = st.axis == 0 ? cx : (st.axis == 1 ? cy : cz);
+      mb_flags(st, cc, less, match);
+    }
+    int eq_tot;
+    const int eqr = block_excl_scan<kChunkBS>(match ? 1 : 0, scan_sm, eq_tot);
+    const bool low = valid && (less || (match && (eq_base + eqr) < st.rank));
+    int low_tot;
+    const int lr = block_excl_scan<kChunkBS>(low ? 1 : 0, scan_sm, low_tot);
+    if (valid) {
+      int dst;
+      if (low) {
+        dst = start + low_base + lr;
+        cmax_low = fmax(cmax_low, cc);
+      } else {
+        dst = start + m + (i - (low_base + lr));
+        cmin_high = fmin(cmin_high, cc);
+      }
+      // as in the one-block round: a wrong selection cannot write outside
+      // the segment
+      if ((low && dst < start + m) || (!low && dst >= start + m && dst < start + n)) {
+        xout[dst] = cx;
+        yout[dst] = cy;
+        zout[dst] = cz;
+        iout[dst] = id;
+      }
+    }
+    low_base += low_tot;
+    eq_base += eq_tot;
+  }
+  cmax_low = block_reduce<kChunkBS>(cmax_low, true, red_sm);
+  cmin_high = block_reduce<kChunkBS>(cmin_high, false, red_sm);
+  if (threadIdx.x == 0) cpart[blockIdx.x] = make_double2(cmax_low, cmin_high);
+}
+
+// split plane and the two child cells / ranges (one wave per segment)
+__global__ __launch_bounds__(64) void k_mb_final(const SegSel* __restrict__ sel, int nchunk,
+                                                 const double2* __restrict__ cpart, double* __restrict__ cells,
+                                                 int32_t* __restrict__ seg_start, int32_t* __restrict__ seg_n,
+                                                 int depth) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x;
+  double a = -INFINITY, b = INFINITY;
+  for (int c = lane; c < nchunk; c += 64) {
+    const double2 v = cpart[(size_t)blockIdx.x * nchunk + c];
+    a = fmax(a, v.x);
+    b = fmin(b, v.y);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a = fmax(a, __shfl_xor(a, d));
+    b = fmin(b, __shfl_xor(b, d));
+  }
+  if (lane != 0) return;
+  const int axis = sel[blockIdx.x].axis;
+  const double plane = 0.5 * (a + b);
+  const int64_t seg = ((int64_t)1 << depth) - 1 + blockIdx.x;
+  const int start = seg_start[seg], n = seg_n[seg], m = n / 2;
+  const int64_t cb = ((int64_t)1 << (depth + 1)) - 1 + 2 * (int64_t)blockIdx.x;
+  for (int k = 0; k < 3; ++k) {
+    const double lo = cells[seg * 6 + k], hi = cells[seg * 6 + 3 + k];
+    cells[cb * 6 + k] = lo;
+    cells[cb * 6 + 3 + k] = hi;
+    cells[(cb + 1) * 6 + k] = lo;
+    cells[(cb + 1) * 6 + 3 + k] = hi;
+  }
+  cells[cb * 6 + 3 + axis] = plane;
+  cells[(cb + 1) * 6 + axis] = plane;
+  seg_start[cb] = start;
+  seg_n[cb] = m;
+  seg_start[cb + 1] = start + m;
+  seg_n[cb + 1] = n - m;
+}
+
 // centre = cell centre, radius = half the cell diagonal (Section 2.1.1)
 __global__ void k_box_geom(const double* __restrict__ cells, const int32_t* __restrict__ seg_start, int depth,
                            int64_t nbox, double* __restrict__ geom, int32_t* __restrict__ start, int32_t n) {
@@ -371,19 +663,66 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, hipS
   HIPCHECK(hipGetLastError());
   dfree(part, s);
 
+  // rounds whose segments all hold at least kMultiMin points (and are few)
+  // go through the chunked kernels; the rest run one block per segment
+  constexpr int64_t kMultiMin = 4 * kChunk;
+  constexpr int64_t kMultiMaxSeg = 512;
+  SegSel* sel = nullptr;
+  unsigned* ghist = nullptr;
+  int2* ccount = nullptr;
+  int2* cbase = nullptr;
+  double2* cpart = nullptr;
+  if (n / 2 >= kMultiMin) {
+    const int64_t nblk = (n + kChunk - 1) / kChunk + kMultiMaxSeg;  // chunks of any multi-block round
+    sel = (SegSel*)dalloc(kMultiMaxSeg * sizeof(SegSel), s);
+    ghist = (unsigned*)dalloc(kMultiMaxSeg * 256 * sizeof(unsigned), s);
+    ccount = (int2*)dalloc(nblk * sizeof(int2), s);
+    cbase = (int2*)dalloc(nblk * sizeof(int2), s);
+    cpart = (double2*)dalloc(nblk * sizeof(double2), s);
+  }
+
   int cur = 0;
   for (int depth = 0; depth < 3 * L; ++depth) {
     const int64_t nsegd = (int64_t)1 << depth;
     const int64_t maxn = (n + nsegd - 1) / nsegd;
+    const int64_t minn = n / nsegd;
     const int o = cur ^ 1;
-    if (maxn > 128)
+    if (minn >= kMultiMin && nsegd <= kMultiMaxSeg) {
+      const int nchunk = (int)((maxn + kChunk - 1) / kChunk);
+      const unsigned nseg = (unsigned)nsegd, nblk = (unsigned)(nsegd * nchunk);
+      k_mb_init<<<nseg, 256, 0, s>>>(cells, seg_n, depth, sel, ghist);
+      HIPCHECK(hipGetLastError());
+      for (int pass = 0; pass < kSelPasses; ++pass) {
+        k_mb_hist<<<nblk, kChunkBS, 0, s>>>(xs[cur], ys[cur], zs[cur], seg_start, seg_n, depth, nchunk, sel, ghist);
+        HIPCHECK(hipGetLastError());
+        k_mb_select<<<nseg, 64, 0, s>>>(sel, ghist);
+        HIPCHECK(hipGetLastError());
+      }
+      k_mb_count<<<nblk, kChunkBS, 0, s>>>(xs[cur], ys[cur], zs[cur], seg_start, seg_n, depth, nchunk, sel, ccount);
+      HIPCHECK(hipGetLastError());
+      k_mb_scan<<<nseg, 64, 0, s>>>(sel, nchunk, ccount, cbase);
+      HIPCHECK(hipGetLastError());
+      k_mb_scatter<<<nblk, kChunkBS, 0, s>>>(xs[cur], ys[cur], zs[cur], ids[cur], xs[o], ys[o], zs[o], ids[o],
+                                             seg_start, seg_n, depth, nchunk, sel, cbase, cpart);
+      HIPCHECK(hipGetLastError());
+      k_mb_final<<<nseg, 64, 0, s>>>(sel, nchunk, cpart, cells, seg_start, seg_n, depth);
+      HIPCHECK(hipGetLastError());
+    } else if (maxn > 128) {
       k_orb_round<256><<<(unsigned)nsegd, 256, 0, s>>>(xs[cur], ys[cur], zs[cur], ids[cur], xs[o], ys[o], zs[o],
                                                        ids[o], cells, seg_start, seg_n, depth);
-    else
+    } else {
       k_orb_round<64><<<(unsigned)nsegd, 64, 0, s>>>(xs[cur], ys[cur], zs[cur], ids[cur], xs[o], ys[o], zs[o],
                                                      ids[o], cells, seg_start, seg_n, depth);
+    }
     HIPCHECK(hipGetLastError());
     cur = o;
+  }
+  if (sel) {
+    dfree(sel, s);
+    dfree(ghist, s);
+    dfree(ccount, s);
+    dfree(cbase, s);
+    dfree(cpart, s);
   }
 
   t.lev.assign(L + 1, Level());

@@ -93,6 +93,9 @@ CASES = [
     ("gmix1500_p0", "gmix", 1_500, 2, 0.5, 0),
     ("uniform1200_p20", "uniform", 1_200, 1, 0.3, 20),
     ("plummer4k_L3_sparse", "plummer", 4_000, 3, 0.45, 7),
+    # coordinates on an 8^3 lattice: long runs of equal keys in the medians of
+    # the chunked (large-segment) bisection rounds
+    ("quantized40k_ties", "quantized", 40_000, 3, 0.5, 4),
 ]
 
 
@@ -103,6 +106,9 @@ def make(gen, n, seed=0):
         return W.gaussian_mixture(n, seed=seed)
     if gen == "plummer":
         return W.plummer(n, seed=seed, charges="pm1")
+    if gen == "quantized":
+        x, y, z, q = W.uniform_cube(n, seed=seed)
+        return np.floor(x * 8) / 8 - 0.5, np.floor(y * 8) / 8 - 0.5, np.floor(z * 8) / 8 - 0.5, q
     raise ValueError(gen)
 
 
