@@ -34,6 +34,14 @@
  *    Section 2.1.1: only children of strongly connected parents are tested.
  *  - Expansion order p = highest degree kept, (p+1)^2 complex terms.
  *  - M2L at every level 1..L, L2L for levels 1..L-1 (reading of Algorithm 3).
+ *
+ * Pins: the test-suite checks every function here against closed forms,
+ * hand-derived golden trees and lists, exactness identities of the
+ * translations, the published truncation bounds, and the reductions of the
+ * whole method to the direct sum (L = 0, theta = 0).  The paper prints no
+ * error values for its convergence experiment (Section 3.1), so the error
+ * levels of the whole method are parity unpinned against numbers of the
+ * paper's own: they are pinned only to the shape of its bound.
  */
 #include <complex.h>
 #include <math.h>
