@@ -231,11 +231,17 @@ HostTables make_host_tables(int p) {
       h.pos[k] = tl::spos(t, sl);
       h.ipos[tl::spos(t, sl)] = k;
     }
-  // MFMA tables: tile matrices of the quarter turn about y (its cosine and sine
-  // blocks; cross entries vanish), factorials, 1/sqrt((n+m)!(n-m)!)
+  // MFMA tables, stored as operand fragments (entry [step][lane] is what lane
+  // `lane` feeds to the k-step `step` of a 16x16x4 chain: row lane % 16,
+  // column 4 step + lane / 16):
+  //  - per tile, the matrix of the quarter turn about y restricted to the
+  //    tile (its cosine and sine blocks; cross entries vanish);
+  //  - per order m, the z-axis translation without its distance powers,
+  //    H_m[a][b] = (-1)^(m+b) (2m+a+b)! u_{m+a,m} u_{m+b,m},
+  //    u_{n,m} = 1/sqrt((n+m)!(n-m)!), a, b < p + 1 - m.
   const std::vector<double> Jy = quarter_turn(p, h.joff, quarter_y);
   const int T = tl::ntiles(p);
-  h.mtab.assign((size_t)T * 16 * 17 + 32 + 256, 0.0);
+  std::vector<double> W((size_t)T * 256, 0.0);
   for (int t = 0; t < T; ++t)
     for (int r = 0; r < 16; ++r)
       for (int c = 0; c < 16; ++c) {
@@ -244,13 +250,26 @@ HostTables make_host_tables(int p) {
         const int n = a.n, sdim = 2 * n + 1;
         const int ia = a.m == 0 ? 0 : 2 * a.m - 1 + a.sine;
         const int ib = b.m == 0 ? 0 : 2 * b.m - 1 + b.sine;
-        h.mtab[(size_t)t * 272 + r * 17 + c] = Jy[h.joff[n] + ia * sdim + ib];
+        W[(size_t)t * 256 + r * 16 + c] = Jy[h.joff[n] + ia * sdim + ib];
       }
-  double* fct = h.mtab.data() + (size_t)T * 272;
-  for (int i = 0; i < 32; ++i) fct[i] = (double)f_all(i);
-  double* uz = fct + 32;
-  for (int m = 0; m <= p; ++m)
-    for (int n = m; n <= p; ++n) uz[16 * m + n] = (double)(1.0L / sqrtl(f_all(n + m) * f_all(n - m)));
+  const int H = tl::hoff(p, p + 1);
+  h.mtab.assign((size_t)T * 4 * 64 + (size_t)H * 64, 0.0);
+  for (int t = 0; t < T; ++t)
+    for (int st = 0; st < 4; ++st)
+      for (int lane = 0; lane < 64; ++lane)
+        h.mtab[((size_t)t * 4 + st) * 64 + lane] = W[(size_t)t * 256 + (lane % 16) * 16 + 4 * st + lane / 16];
+  double* hf = h.mtab.data() + (size_t)T * 4 * 64;
+  for (int m = 0; m <= p; ++m) {
+    const int K = p + 1 - m;
+    for (int st = 0; st < tl::hsteps(p, m); ++st)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int a = lane % 16, b = 4 * st + lane / 16;
+        if (a >= K || b >= K) continue;
+        const long double u = 1.0L / sqrtl(f_all(2 * m + a) * f_all(a) * f_all(2 * m + b) * f_all(b));
+        const long double sg = ((m + b) & 1) ? -1.0L : 1.0L;
+        hf[((size_t)tl::hoff(p, m) + st) * 64 + lane] = (double)(sg * f_all(2 * m + a + b) * u);
+      }
+  }
   return h;
 }
 

@@ -33,6 +33,14 @@ __host__ __device__ constexpr int spos(int t, int s) { return 16 * t + 4 * (s & 
 // first row of order m in the z-translation buffer (rows (m, n), n = m..p)
 __host__ __device__ constexpr int zoff(int p, int m) { return m * (p + 1) - m * (m - 1) / 2; }
 __host__ __device__ constexpr int zrows(int p) { return zoff(p, p + 1); }
+// k-steps of 4 of the order-m z-translation (p + 1 - m rows), and the first
+// step of order m in the operator table
+__host__ __device__ constexpr int hsteps(int p, int m) { return (p + 1 - m + 3) / 4; }
+__host__ __device__ constexpr int hoff(int p, int m) {
+  int o = 0;
+  for (int k = 0; k < m; ++k) o += hsteps(p, k);
+  return o;
+}
 
 struct Slot {
   int n, m;

@@ -127,6 +127,21 @@ def test_parity_full(torch, F, orc, name, gen, n, L, theta, p):
     gt.free()
 
 
+@pytest.mark.parametrize("p", list(range(16)))
+def test_parity_far_field_every_mfma_order(torch, F, orc, p):
+    """Far field (M2L and the translations) at every order the matrix-core
+    M2L takes, on a two-level tree (about 24 weak pairs per leaf: one full
+    and one partial batch of 16)."""
+    say(f"[orders] p={p}")
+    x, y, z, q = make("gmix", 2_000, seed=4)
+    ot = orc.Tree(x, y, z, 2, 0.6)
+    gt = gpu_tree(torch, F, x, y, z, 2, 0.6)
+    ref = ot.evaluate(q, p, parts=2)
+    got = gpu_eval(torch, F, gt, q, p, parts=2)
+    assert_close(got, ref, what=f"far p={p}")
+    gt.free()
+
+
 EDGE = [
     ("one_point_L0", np.array([[0.3, 0.2, 0.1]]), 0),
     ("one_point_L2", np.array([[0.3, 0.2, 0.1]]), 2),
