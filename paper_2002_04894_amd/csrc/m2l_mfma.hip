@@ -63,8 +63,9 @@ struct Cfg {
   static constexpr int RSTRIDE = 18;  // row stride of the pair-sum buffer (no bank conflicts)
   // the pair-sum rounds reuse the z buffer
   static constexpr int ZBUF = 16 * (ZR + 4) > 64 * RSTRIDE ? 16 * (ZR + 4) : 64 * RSTRIDE;
-  // per pair: (cos, sin)(m (theta + pi)), (cos, sin)(m (alpha + pi)), m = 0..P
-  static constexpr int TRIG = 4 * (P + 1);
+  // per pair: (cos, sin)(m (theta + pi)), (cos, sin)(m (alpha + pi)), m = 0..P;
+  // 16 more bytes per pair so that the 16 pair columns hit different banks
+  static constexpr int TRIG = 4 * (P + 1) + 2;
   static constexpr int SHARED = T * 256 + H * 64;
   static constexpr int PERWAVE = 16 * TRIG + ZBUF;
   static constexpr int LDS = SHARED + 4 * PERWAVE;
@@ -77,20 +78,63 @@ __device__ __forceinline__ int level_of2(const LevelView& lv, int64_t gid) {
   return l;
 }
 
-// order m of slot s of tile t, clamped to P for padding slots
+// Slot s of tile t as a coefficient position (degree n, order m), or a
+// padding slot (pos = 0).  The always-zero sine slot of order 0 counts as a
+// position: it is carried along like any coefficient.
+struct Pos {
+  int pos, n, m;
+};
 template <int P>
-__device__ __forceinline__ int slot_m(int t, int s) {
+__host__ __device__ constexpr Pos slot_pos(int t, int s) {
   constexpr int NP = tl::npairs(P);
-  int m;
   if (t < 2 * NP) {
-    const int a = t < NP ? t : t - NP;
-    m = s <= a ? s : s - a - 1;
-  } else if (tl::has_mixed(P) && t == tl::mixed_tile(P)) {
-    m = s < 8 ? s : s - 8;
-  } else {
-    m = s;
+    const int a = t < NP ? t : t - NP, b = P - 1 - a;
+    if (s <= a) return Pos{1, a, s};
+    if (s <= a + 1 + b) return Pos{1, b, s - a - 1};
+    return Pos{0, 0, 0};
   }
-  return m < P ? m : P;
+  if (tl::has_mixed(P) && t == tl::mixed_tile(P)) {
+    const int h = (P - 1) / 2;
+    if (s <= h) return Pos{1, h, s};
+    if (s >= 8 && s <= 8 + h) return Pos{1, h, s - 8};
+    return Pos{0, 0, 0};
+  }
+  return s <= P ? Pos{1, P, s} : Pos{0, 0, 0};
+}
+
+// The four lanes groups g = 0..3 hold slots 4i + g of register i.  Along g
+// they form at most three runs: within a run either padding, or one degree n
+// with orders m = m0 + g.
+struct Quad {
+  int nseg;
+  int end[3];  // run k covers g < end[k]
+  int pad[3], n[3], m0[3];
+};
+template <int P>
+__host__ __device__ constexpr Quad quad(int t, int i) {
+  Quad q{0, {4, 4, 4}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int g = 0; g < 4; ++g) {
+    const Pos d = slot_pos<P>(t, 4 * i + g);
+    const int k = q.nseg - 1;
+    const bool same = q.nseg > 0 && ((q.pad[k] && !d.pos) ||
+                                    (!q.pad[k] && d.pos && d.n == q.n[k] && d.m == q.m0[k] + g));
+    if (!same) {
+      if (q.nseg > 0) q.end[q.nseg - 1] = g;
+      q.pad[q.nseg] = d.pos ? 0 : 1;
+      q.n[q.nseg] = d.n;
+      q.m0[q.nseg] = d.m - g;
+      ++q.nseg;
+    }
+  }
+  q.end[q.nseg - 1] = 4;
+  return q;
+}
+
+// pick v[k] for this lane's run of q
+__device__ __forceinline__ int pick(const Quad& q, int g, int v0, int v1, int v2) {
+  if (q.nseg == 1) return v0;
+  const int w = g < q.end[0] ? v0 : v1;
+  return q.nseg == 2 ? w : (g < q.end[1] ? w : v2);
 }
 
 // 1 if register i of tile t holds sine-block slots (fixed per (t, i))
@@ -103,14 +147,39 @@ __host__ __device__ constexpr int reg_sine(int t, int i) {
   return t == tl::top_s(P) ? 1 : 0;
 }
 
-// (c, s) <- (cos c - sgn sin s, sgn sin c + cos s) for every (cosine, sine)
-// partner pair; cs points at the (cos m g, sin m g) pairs of this lane's pair
-template <int P>
-__device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g) {
+// Per-lane views of the small tables.  csg[k] points at (cos, sin) of order
+// k - 4 + g of this lane's pair (k covers the run offsets m0 = -4 .. 15), so
+// the order of a slot is a constant offset; pw[n] = (1/rho)^n.
+struct PairView {
+  const double* csg;
+};
+
+// (c, s) <- f (cos c - sgn sin s, sgn sin c + cos s) for every (cosine, sine)
+// partner pair, f = ir^(n + SHIFT) (SCALE) or 1; cs: this lane's (cos, sin)
+// table shifted by 2 (g - 4)
+template <int P, bool SCALE, int SHIFT>
+__device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g, double ir) {
   constexpr int NP = tl::npairs(P);
-  auto rot = [&](double& c, double& s, int m) {
-    const d2 v = *(const d2*)(cs + 2 * m);
-    const double co = v.x, si = sgn * v.y;
+  double pw[SCALE ? P + 2 : 1];  // (1/rho)^n, built here to keep it short-lived
+  pw[0] = 1.0;
+  if constexpr (SCALE) {
+#pragma unroll
+    for (int n = 1; n <= P + 1; ++n) pw[n] = pw[n - 1] * ir;
+  }
+  auto rot = [&](double& c, double& s, int t, int i) {
+    const Quad q = quad<P>(t, i);
+    const int k0 = 2 * (q.m0[0] + 4), k1 = 2 * (q.m0[1] + 4), k2 = 2 * (q.m0[2] + 4);
+    // a padding run reads any finite entry: its coefficients are zero
+    const d2 v = *(const d2*)(cs + pick(q, g, q.pad[0] ? 8 : k0, q.pad[1] ? 8 : k1, q.pad[2] ? 8 : k2));
+    double co = v.x, si = sgn * v.y;
+    if constexpr (SCALE) {
+      const double f = q.nseg == 1 ? pw[q.n[0] + SHIFT]
+                                   : (g < q.end[0] ? pw[q.n[0] + SHIFT]
+                                                   : (q.nseg == 2 || g < q.end[1] ? pw[q.n[1] + SHIFT]
+                                                                                 : pw[q.n[2] + SHIFT]));
+      co *= f;
+      si *= f;
+    }
     const double nc = co * c - si * s;
     const double ns = si * c + co * s;
     c = nc;
@@ -121,7 +190,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       double c = st[a][i], s = st[NP + a][i];
-      rot(c, s, slot_m<P>(a, 4 * i + g));
+      rot(c, s, a, i);
       st[a][i] = c;
       st[NP + a][i] = s;
     }
@@ -131,7 +200,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       double c = st[t][i], s = st[t][i + 2];
-      rot(c, s, slot_m<P>(t, 4 * i + g));
+      rot(c, s, t, i);
       st[t][i] = c;
       st[t][i + 2] = s;
     }
@@ -141,7 +210,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       double c = st[tc][i], s = st[ts][i];
-      rot(c, s, slot_m<P>(tc, 4 * i + g));
+      rot(c, s, tc, i);
       st[tc][i] = c;
       st[ts][i] = s;
     }
@@ -161,67 +230,67 @@ __device__ __forceinline__ void japply(d4* st, const double* jf, int lane) {
   }
 }
 
-// z-buffer row of slot s of tile t: the row (m, n) of a coefficient, or
-// `other` for a padding slot or an always-zero sine slot
+// z buffer addressing: zl[k] points at row zoff(m) - m of this lane's column
+// for m = k - 4 + g (so that row (m, n) is zl[k] + 16 n), zd at the
+// write-only row, zz at the zero row
+struct ZView {
+  double* zl[20];
+  double* zd;
+  const double* zz;
+};
+
 template <int P>
-__device__ __forceinline__ int zrow(int t, int s, int other) {
-  const tl::Slot d = tl::decode(P, t, s);
-  return d.valid ? tl::zoff(P, d.m) + d.n - d.m : other;
+__device__ __forceinline__ double* zslot(const ZView& z, int t, int i, int g, bool for_read) {
+  const Quad q = quad<P>(t, i);
+  double* other = for_read ? (double*)z.zz : z.zd;
+  double* a0 = q.pad[0] ? other : z.zl[q.m0[0] + 4] + 16 * q.n[0];
+  if (q.nseg == 1) return a0;
+  double* a1 = q.pad[1] ? other : z.zl[q.m0[1] + 4] + 16 * q.n[1];
+  double* w = g < q.end[0] ? a0 : a1;
+  if (q.nseg == 2) return w;
+  double* a2 = q.pad[2] ? other : z.zl[q.m0[2] + 4] + 16 * q.n[2];
+  return g < q.end[1] ? w : a2;
 }
 
-// z-axis translation of the cosine (SINE = 0) or sine blocks
+// z-axis translation of the cosine (SINE = 0) or sine blocks; the input is
+// already scaled by (1/rho)^n and the output by (1/rho)^(j+1) is applied by
+// the next rotation
 template <int P, int SINE>
-__device__ __forceinline__ void ztrans_part(d4* st, double* zb, const double* hf, double ir, int lane) {
-  using C = Cfg<P>;
-  constexpr int T = C::T;
-  const int r16 = lane & 15, g = lane >> 4;
-  // to order-major rows
+__device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol, const double* hf, int lane) {
+  constexpr int T = tl::ntiles(P);
+  const int g = lane >> 4;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE) continue;
-      zb[zrow<P>(t, 4 * i + g, C::ZDUMMY) * 16 + r16] = st[t][i];
+      *zslot<P>(z, t, i, g, false) = st[t][i];
     }
   }
   wave_lds_fence();
-  // per order m: L'(m + a) = ir^(m + a + 1) sum_b H_m[a][b] ir^(m + b) M'(m + b)
-  double irg = 1.0;  // ir^g
-  for (int k = 0; k < g; ++k) irg *= ir;
-  const double ir2 = ir * ir, ir4 = ir2 * ir2;
-  double pm = SINE ? ir : 1.0;  // ir^m
+  // zcol: this lane's column at row g
 #pragma unroll
   for (int m = SINE; m <= P; ++m) {
     const int K = P + 1 - m;
     const int zo = tl::zoff(P, m);
     const int ho = tl::hoff(P, m);
     d4 d = {0.0, 0.0, 0.0, 0.0};
-    double w = pm * irg;  // ir^(m + 4k + g)
 #pragma unroll
-    for (int k = 0; k < tl::hsteps(P, m); ++k) {
-      const double bv = zb[(zo + 4 * k + g) * 16 + r16] * w;
-      d = mfma(hf[(ho + k) * 64 + lane], bv, d);
-      w *= ir4;
-    }
-    double wo = pm * irg * ir;  // ir^(m + 4i + g + 1)
+    for (int k = 0; k < tl::hsteps(P, m); ++k) d = mfma(hf[(ho + k) * 64 + lane], zcol[(zo + 4 * k) * 16], d);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      if (4 * i < K) {
-        const int row = (4 * i + 3 < K || 4 * i + g < K) ? zo + 4 * i + g : C::ZDUMMY;
-        zb[row * 16 + r16] = d[i] * wo;
-      }
-      wo *= ir4;
+      if (4 * i >= K) continue;
+      double* dst = (4 * i + 3 < K || 4 * i + g < K) ? zcol + (zo + 4 * i) * 16 : z.zd;
+      *dst = d[i];
     }
-    pm *= ir;
   }
   wave_lds_fence();
-  // back to tiles
 #pragma unroll
   for (int t = 0; t < T; ++t) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE) continue;
-      st[t][i] = zb[zrow<P>(t, 4 * i + g, C::ZZERO) * 16 + r16];
+      st[t][i] = *zslot<P>(z, t, i, g, true);
     }
   }
   wave_lds_fence();
@@ -247,17 +316,18 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
   __syncthreads();
 
   double* tp = trig + r16 * C::TRIG;  // this lane's pair
-  const double* cs_t = tp;
-  const double* cs_a = tp + 2 * (P + 1);
-  // the coefficient each lane accumulates in round r: slot lane % 16 of tile
-  // 4 r + lane / 16, stored with the sign (-1)^m of the final D
-  double sgn_out[C::NR];
+  // (cos, sin) tables shifted so that entry 2 (m0 + 4) is order m0 + g
+  const double* cs_t = tp + 2 * (g - 4);
+  const double* cs_a = tp + 2 * (P + 1) + 2 * (g - 4);
+  ZView z;
 #pragma unroll
-  for (int r = 0; r < C::NR; ++r) {
-    const int t = 4 * r + (lane >> 4);
-    const tl::Slot d = tl::decode(P, t < T ? t : 0, lane & 15);
-    sgn_out[r] = (d.m & 1) ? -1.0 : 1.0;
+  for (int k = 0; k < 20; ++k) {
+    const int m = k - 4 + g;
+    z.zl[k] = zb + 16 * (tl::zoff(P, m) - m) + r16;
   }
+  z.zd = zb + 16 * C::ZDUMMY + r16;
+  z.zz = zb + 16 * C::ZZERO + r16;
+  double* zcol = zb + 16 * g + r16;
 
   // persistent waves: each takes the next target of the longest-first order
   // until the queue is empty (no block-wide barrier below this point)
@@ -295,14 +365,16 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
       }
       const double rxy2 = dx * dx + dy * dy;
       const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
-      const double ir = valid ? 1.0 / rho : 0.0;
+      const double irho = 1.0 / rho;
+      const double irxy = rxy > 0.0 ? 1.0 / rxy : 0.0;
+      const double ir = valid ? irho : 0.0;
       // (cos, sin)(m (angle + pi)) by the angle-addition recurrence; lane
       // groups 0, 2 build the theta table and 1, 3 the alpha table (groups 2
       // and 3 write the same values to the same words as 0 and 1)
       {
         const bool ta = (g & 1) != 0;
-        const double c1 = ta ? -dz / rho : (rxy > 0.0 ? -dy / rxy : 0.0);
-        const double s1 = ta ? -rxy / rho : (rxy > 0.0 ? -dx / rxy : -1.0);
+        const double c1 = ta ? -dz * irho : -dy * irxy;
+        const double s1 = ta ? -rxy * irho : (rxy > 0.0 ? -dx * irxy : -1.0);
         double* dst = tp + (ta ? 2 * (P + 1) : 0);
         double c = 1.0, s = 0.0;
 #pragma unroll
@@ -319,16 +391,16 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
       for (int t = 0; t < T; ++t) st[t] = *(const d4*)(src + 16 * t);
       wave_lds_fence();
 
-      rotz<P>(st, cs_t, 1.0, g);
+      rotz<P, false, 0>(st, cs_t, 1.0, g, ir);
       japply<P>(st, jf, lane);
-      rotz<P>(st, cs_a, 1.0, g);
+      rotz<P, true, 0>(st, cs_a, 1.0, g, ir);  // and (1/rho)^n
       japply<P>(st, jf, lane);
-      ztrans_part<P, 0>(st, zb, hf, ir, lane);
-      ztrans_part<P, 1>(st, zb, hf, ir, lane);
+      ztrans_part<P, 0>(st, z, zcol, hf, lane);
+      ztrans_part<P, 1>(st, z, zcol, hf, lane);
       japply<P>(st, jf, lane);
-      rotz<P>(st, cs_a, -1.0, g);
+      rotz<P, true, 1>(st, cs_a, -1.0, g, ir);  // and (1/rho)^(j+1)
       japply<P>(st, jf, lane);
-      rotz<P>(st, cs_t, -1.0, g);
+      rotz<P, false, 0>(st, cs_t, -1.0, g, ir);
 
       // sum over the 16 pairs: four tiles per round through LDS; lane L adds
       // up row L (slot L % 16 of tile 4 r + L / 16)
@@ -352,11 +424,16 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
         wave_lds_fence();
       }
     }
+    // lane L holds slot L % 16 of tile 4 r + L / 16; the final D is the
+    // sign (-1)^m
     double* dst = Lx + (size_t)gid * S;
 #pragma unroll
     for (int r = 0; r < C::NR; ++r) {
       const int t = 4 * r + (lane >> 4);
-      if (t < T) dst[tl::spos(t, lane & 15)] = sgn_out[r] * acc[r];
+      if (t < T) {
+        const Pos d = slot_pos<P>(t, lane & 15);
+        dst[tl::spos(t, lane & 15)] = (d.m & 1) ? -acc[r] : acc[r];
+      }
     }
   }
 }
