@@ -61,6 +61,14 @@ void release(Tree& t) {
   f(t.perm);
   f(t.m2l_order);
   t.m2l_order = nullptr;
+  f(t.p2p_seg_leaf);
+  f(t.p2p_seg_e0);
+  f(t.p2p_leaf_seg);
+  f(t.p2p_leaf_part);
+  t.p2p_seg_leaf = nullptr;
+  t.p2p_seg_e0 = nullptr;
+  t.p2p_leaf_seg = nullptr;
+  t.p2p_leaf_part = nullptr;
   for (Level& V : t.lev) {
     f(V.geom);
     f(V.start);
@@ -195,7 +203,6 @@ fmm_tree* build_impl(const double* x, const double* y, const double* z, int64_t 
   t.L = levels;
   t.theta = theta;
   t.stream = s;
-  t.p2p_pairs = -1;
   try {
     fmm::timer().reset();
     fmm::timer().begin(FMM_PH_TREE, s);
@@ -203,6 +210,7 @@ fmm_tree* build_impl(const double* x, const double* y, const double* z, int64_t 
     fmm::timer().end(FMM_PH_TREE, s);
     fmm::timer().begin(FMM_PH_LISTS, s);
     fmm::lists_build(t, s);
+    fmm::p2p_plan(t, s);
     fmm::timer().end(FMM_PH_LISTS, s);
   } catch (...) {
     fmm::release(t);
@@ -328,8 +336,7 @@ int fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int6
 
 int fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs) {
   return fmm::guarded([&] {
-    fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
-    if (t.p2p_pairs < 0) fmm::tree_compute_stats(t, t.stream);
+    const fmm::Tree& t = get(tree);
     if (m2l_pairs) *m2l_pairs = t.m2l_pairs;
     if (p2p_pairs) *p2p_pairs = t.p2p_pairs;
   });
@@ -362,7 +369,9 @@ size_t fmm_bytes_estimate(int64_t n, int levels, double theta, int p) {
   const double th = theta > 0.05 ? theta : 0.05;
   // weak and strong links per box on a uniform lattice grow like theta^-3
   const double links = 650.0 * (0.125 / (th * th * th)) + 100.0;
-  const size_t pts = (size_t)n * (2 * 28 + 8 + 4 * 8 + 8);
+  // points: coordinates (two copies during the build), permutation, charges,
+  // far field, and an allowance for the near-field partial sums
+  const size_t pts = (size_t)n * (2 * 28 + 8 + 4 * 8 + 8 + 32);
   const size_t geo = (size_t)nbox * (10 * 8 + 4 + 16) + ((size_t)2 << (3 * levels)) * (6 * 8 + 8);
   const size_t lists = (size_t)((double)nbox * links * 4.0);
   const size_t expn = (size_t)nbox * (size_t)(p + 1) * (p + 1) * 8 * 2;

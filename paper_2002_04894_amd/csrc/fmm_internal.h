@@ -72,6 +72,14 @@ struct Tree {
   int32_t* m2l_order = nullptr;  // M2L targets (box id - 1), longest weak list first
   int64_t m2l_pairs = 0;
   int64_t p2p_pairs = 0;
+  // near-field work items: each leaf's strong list cut into segments of about
+  // the same number of source points
+  int64_t p2p_nseg = 0;
+  int32_t* p2p_seg_leaf = nullptr;   // [nseg] target leaf
+  int64_t* p2p_seg_e0 = nullptr;     // [nseg] first strong-list entry
+  int64_t* p2p_leaf_seg = nullptr;   // [nleaf + 1] first segment of each leaf
+  int64_t* p2p_leaf_part = nullptr;  // [nleaf + 1] first partial sum of each split leaf
+  int64_t p2p_npart = 0;             // partial sums (target x segment) of split leaves
   LevelView view() const;
 };
 
@@ -107,11 +115,12 @@ PhaseTimer& timer();
 // ---- launch wrappers ----
 void tree_build(Tree& t, const double* x, const double* y, const double* z, hipStream_t s);
 void lists_build(Tree& t, hipStream_t s);
-void tree_compute_stats(Tree& t, hipStream_t s);
+void p2p_plan(Tree& t, hipStream_t s);
 void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, double* ex, double* ey, double* ez,
               hipStream_t s);
 
 // exclusive scan of int32 counts into int64 offsets (out[n] = total + base)
 void scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t base, hipStream_t s);
+void scan_counts(const int64_t* in, int64_t* out, int64_t n, int64_t base, hipStream_t s);
 
 }  // namespace fmm

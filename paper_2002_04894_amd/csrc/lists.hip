@@ -119,7 +119,8 @@ __device__ __forceinline__ int64_t block_excl_scan64(int64_t v, int64_t* sm, int
   return off + inc - v;
 }
 
-__global__ void k_scan_tiles(const int32_t* __restrict__ in, int64_t* __restrict__ out, int64_t n,
+template <class TIn>
+__global__ void k_scan_tiles(const TIn* __restrict__ in, int64_t* __restrict__ out, int64_t n,
                              int64_t* __restrict__ tile_sums) {
   __shared__ int64_t sm[kScanBS / 64];
   const int64_t t0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -157,31 +158,15 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* 
   if (i < n) out[i] += tile_off[i / kScanTile];
 }
 
-// P2P work count: sum over leaves of n_i * sum_{j in strong(i)} n_j
-__global__ void k_p2p_count(int64_t nleaf, const int32_t* __restrict__ start, const int64_t* __restrict__ s_off,
-                            const int32_t* __restrict__ s_idx, unsigned long long* __restrict__ acc) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long v = 0;
-  if (i < nleaf) {
-    int64_t src = 0;
-    for (int64_t e = s_off[i]; e < s_off[i + 1]; ++e) {
-      const int j = s_idx[e];
-      src += start[j + 1] - start[j];
-    }
-    v = (unsigned long long)((int64_t)(start[i + 1] - start[i]) * src);
-  }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  if ((threadIdx.x & 63) == 0) atomicAdd(acc, v);
-}
-
 }  // namespace
 
-void scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t base, hipStream_t s) {
+namespace {
+template <class TIn>
+void scan_any(const TIn* in, int64_t* out, int64_t n, int64_t base, hipStream_t s) {
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   int64_t* sums = (int64_t*)dalloc((ntiles + 1) * sizeof(int64_t), s);
   if (ntiles > 0) {
-    k_scan_tiles<<<(unsigned)ntiles, kScanBS, 0, s>>>(in, out, n, sums);
+    k_scan_tiles<TIn><<<(unsigned)ntiles, kScanBS, 0, s>>>(in, out, n, sums);
     HIPCHECK(hipGetLastError());
   }
   k_scan_sums<<<1, kScanBS, 0, s>>>(sums, ntiles, base, out + n);
@@ -191,6 +176,14 @@ void scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t base, hipSt
     HIPCHECK(hipGetLastError());
   }
   dfree(sums, s);
+}
+}  // namespace
+
+void scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t base, hipStream_t s) {
+  scan_any(in, out, n, base, s);
+}
+void scan_counts(const int64_t* in, int64_t* out, int64_t n, int64_t base, hipStream_t s) {
+  scan_any(in, out, n, base, s);
 }
 
 void lists_build(Tree& t, hipStream_t s) {
@@ -268,19 +261,6 @@ void lists_build(Tree& t, hipStream_t s) {
     dfree(hist, s);
     dfree(cursor, s);
   }
-}
-
-void tree_compute_stats(Tree& t, hipStream_t s) {
-  const Level& V = t.lev[t.L];
-  unsigned long long* acc = (unsigned long long*)dalloc(sizeof(unsigned long long), s);
-  HIPCHECK(hipMemsetAsync(acc, 0, sizeof(unsigned long long), s));
-  k_p2p_count<<<(unsigned)((V.nbox + 255) / 256), 256, 0, s>>>(V.nbox, V.start, V.s_off, V.s_idx, acc);
-  HIPCHECK(hipGetLastError());
-  unsigned long long h = 0;
-  HIPCHECK(hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  dfree(acc, s);
-  t.p2p_pairs = (int64_t)h - t.n;
 }
 
 }  // namespace fmm

@@ -5,9 +5,14 @@
 // strongly connected to i (i itself included), phi_t += q_s / r and
 // E_t += q_s (x_t - x_s) / r^3, skipping pairs at distance 0 (this removes
 // the self term j = i of eq. (2.1)).  Each target pulls from its full list
-// (gather form: no atomics, deterministic).  One 64-lane workgroup per leaf,
-// lanes over targets (and over 2 or 4 source streams for small leaves);
-// source points are staged through LDS and read back as broadcasts.
+// (gather form: no atomics, deterministic).  On clustered data the strong
+// lists of a few leaves hold far more sources than the rest, so each list is
+// cut into segments of about kP2PSeg source points (a plan made once per
+// tree); one 64-lane workgroup takes one segment.  A leaf with one segment
+// writes its result directly; the segments of a split leaf write partial sums
+// that a second pass adds up in segment order.
+#include <algorithm>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -35,115 +40,333 @@ __device__ __forceinline__ double rsqrt_nr(double r2) {
   return r2 > 0.0 ? y1 : 0.0;
 }
 
-// Leaves are mapped to blocks so that consecutive leaves (whose strong
-// lists overlap) run on the same XCD and share its L2.
+// Work items (segments, in leaf order) are mapped to blocks so that
+// consecutive ones, whose sources overlap, run on the same XCD and share its
+// L2.
 __device__ __forceinline__ int64_t xcd_leaf(int64_t nleaf) {
   const int64_t per = (nleaf + 7) / 8;
   return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-constexpr int kP2PBuf = 512;  // source points staged per round (x, y, z, q)
+constexpr int kP2PBuf = 512;     // source points staged per chunk (x, y, z, q)
+constexpr int64_t kP2PSeg = 8192;  // source points per work item (about)
 
-__global__ __launch_bounds__(64) void k_p2p(int64_t nleaf, const int32_t* __restrict__ start,
+// ---- the plan: one wave per leaf walks its strong list 64 entries at a
+// time.  Entry e starts a segment when it is the first of the list or when
+// floor(sources before e / kP2PSeg) changes at e.
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t t = __shfl_up(v, d);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_seg_plan(int64_t nleaf, const int32_t* __restrict__ start,
+                                                  const int64_t* __restrict__ s_off, const int32_t* __restrict__ s_idx,
+                                                  int32_t* __restrict__ nseg, int64_t* __restrict__ work,
+                                                  const int64_t* __restrict__ leaf_seg, int32_t* __restrict__ seg_leaf,
+                                                  int64_t* __restrict__ seg_e0) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nleaf) return;
+  const int64_t e0 = s_off[i], e1 = s_off[i + 1];
+  const uint64_t below = (1ull << lane) - 1ull;
+  int64_t carry = 0;  // sources of the entries before this chunk
+  int prev_last = 0;  // sources of the entry just before this chunk
+  int64_t flags = 0;  // segments started so far
+  const int64_t base = FILL ? leaf_seg[i] : 0;
+  for (int64_t k0 = e0; k0 < e1; k0 += 64) {
+    const int64_t e = k0 + lane;
+    const bool valid = e < e1;
+    int cnt = 0;
+    if (valid) {
+      const int j = s_idx[e];
+      cnt = start[j + 1] - start[j];
+    }
+    const int64_t incl = wave_incl_scan64(cnt, lane);
+    const int64_t excl = carry + incl - cnt;
+    const int up = __shfl_up(cnt, 1);
+    const int prev = lane == 0 ? prev_last : up;
+    const bool flag = valid && (e == e0 || excl / kP2PSeg != (excl - prev) / kP2PSeg);
+    const uint64_t m = __ballot(flag);
+    if (FILL && flag) {
+      const int64_t pos = base + flags + __popcll(m & below);
+      seg_leaf[pos] = (int32_t)i;
+      seg_e0[pos] = e;
+    }
+    flags += __popcll(m);
+    carry += __shfl(incl, 63);
+    prev_last = __shfl(cnt, 63);
+  }
+  if (!FILL && lane == 0) {
+    nseg[i] = (int32_t)flags;
+    work[i] = (int64_t)(start[i + 1] - start[i]) * carry;  // interactions of this leaf
+  }
+}
+
+// partial sums needed by leaf i: one per target and segment when split
+__global__ void k_part_count(int64_t nleaf, const int32_t* __restrict__ start, const int32_t* __restrict__ nseg,
+                             int64_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nleaf) cnt[i] = nseg[i] > 1 ? (int64_t)nseg[i] * (start[i + 1] - start[i]) : 0;
+}
+
+__global__ void k_sum64(int64_t n, const int64_t* __restrict__ v, unsigned long long* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long x = i < n ? (unsigned long long)v[i] : 0ull;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  if ((threadIdx.x & 63) == 0) atomicAdd(acc, x);
+}
+
+// One 64-lane workgroup per segment.  Each lane holds two targets, t and
+// t + TT, and one of R = 64 / TT source streams, so every source read from
+// LDS serves two interactions.  Sources are staged in chunks of up to kP2PBuf
+// points gathered from consecutive entries of the segment: the lanes take the
+// chunk's points in a flat order, so all their loads are in flight together.
+__global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restrict__ seg_leaf,
+                                            const int64_t* __restrict__ seg_e0, const int64_t* __restrict__ leaf_seg,
+                                            const int64_t* __restrict__ leaf_part, const int32_t* __restrict__ start,
                                             const int64_t* __restrict__ s_off, const int32_t* __restrict__ s_idx,
                                             const double* __restrict__ px, const double* __restrict__ py,
                                             const double* __restrict__ pz, const double* __restrict__ qt,
-                                            const int32_t* __restrict__ perm, int near,
-                                            const double* __restrict__ f0, const double* __restrict__ f1,
-                                            const double* __restrict__ f2, const double* __restrict__ f3,
+                                            const int32_t* __restrict__ perm, const double* __restrict__ f0,
+                                            const double* __restrict__ f1, const double* __restrict__ f2,
+                                            const double* __restrict__ f3, double4* __restrict__ part,
                                             double* __restrict__ pot, double* __restrict__ ex,
                                             double* __restrict__ ey, double* __restrict__ ez) {
   __shared__ double4 buf[kP2PBuf];
-  const int64_t b = xcd_leaf(nleaf);
-  if (b >= nleaf) return;
+  const int64_t g = xcd_leaf(nseg);
+  if (g >= nseg) return;
   const int lane = threadIdx.x;
+  const int64_t b = seg_leaf[g];
+  const int64_t sb = leaf_seg[b], ns = leaf_seg[b + 1] - sb, r = g - sb;
+  const int64_t e0 = seg_e0[g], e1 = r + 1 < ns ? seg_e0[g + 1] : s_off[b + 1];
   const int t0 = start[b], t1 = start[b + 1];
   const int nt = t1 - t0;
-  const int64_t e0 = s_off[b], e1 = s_off[b + 1];
-  // lanes = (target, split): small leaves split the sources over 2 or 4 lane groups
-  const int TT = nt <= 16 ? 16 : (nt <= 32 ? 32 : 64);
+  double4* pout = ns > 1 ? part + leaf_part[b] + r * nt : nullptr;  // partial sums, by target - t0
+  // lanes = (target pair, source stream)
+  const int TT = nt <= 16 ? 8 : (nt <= 32 ? 16 : (nt <= 64 ? 32 : 64));
   const int R = 64 / TT;
   const int tl = lane % TT, h = lane / TT;
-  for (int c0 = t0; c0 < t1; c0 += TT) {
-    const int t = c0 + tl;
-    const bool valid = t < t1;
-    const int tt = valid ? t : t0;
-    const double xt = px[tt], yt = py[tt], zt = pz[tt];
-    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int c0 = t0; c0 < t1; c0 += 2 * TT) {
+    const int ta = c0 + tl, tb = c0 + tl + TT;
+    const bool va = ta < t1, vb = tb < t1;
+    const int ua = va ? ta : t0, ub = vb ? tb : t0;
+    const double xa = px[ua], ya = py[ua], za = pz[ua];
+    const double xb = px[ub], yb = py[ub], zb = pz[ub];
+    double fa = 0.0, gxa = 0.0, gya = 0.0, gza = 0.0;
+    double fb = 0.0, gxb = 0.0, gyb = 0.0, gzb = 0.0;
     auto interact = [&](const double4 s) {
-      const double dx = xt - s.x, dy = yt - s.y, dz = zt - s.z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const double inv = rsqrt_nr(r2);
-      const double qi = s.w * inv;
-      const double qi3 = qi * inv * inv;
-      f += qi;
-      gx += qi3 * dx;
-      gy += qi3 * dy;
-      gz += qi3 * dz;
+      {
+        const double dx = xa - s.x, dy = ya - s.y, dz = za - s.z;
+        const double inv = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+        const double qi = s.w * inv;
+        const double qi3 = qi * inv * inv;
+        fa += qi;
+        gxa += qi3 * dx;
+        gya += qi3 * dy;
+        gza += qi3 * dz;
+      }
+      {
+        const double dx = xb - s.x, dy = yb - s.y, dz = zb - s.z;
+        const double inv = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+        const double qi = s.w * inv;
+        const double qi3 = qi * inv * inv;
+        fb += qi;
+        gxb += qi3 * dx;
+        gyb += qi3 * dy;
+        gzb += qi3 * dz;
+      }
     };
-    auto flush = [&](int fill) {
+    int64_t e = e0;  // next entry
+    int off = 0;     // points of entry e already staged
+    while (e < e1) {
+      // up to 16 entries from e on: lane q < 16 takes entry e + q
+      int base = 0, cnt = 0;
+      if (lane < 16 && e + lane < e1) {
+        const int j = s_idx[e + lane];
+        base = start[j] + (lane == 0 ? off : 0);
+        cnt = start[j + 1] - base;
+      }
+      int pre = cnt;  // inclusive prefix over lanes 0..15
+#pragma unroll
+      for (int d = 1; d < 16; d <<= 1) {
+        const int v = __shfl_up(pre, d, 16);
+        if ((lane & 15) >= d) pre += v;
+      }
+      const int all = __shfl(pre, 15);
+      const int fill = all < kP2PBuf ? all : kP2PBuf;
+      const int avail = (int)(e1 - e < 16 ? e1 - e : 16);
+      // flat point f of the chunk lies in entry q: pre[q-1] <= f < pre[q];
+      // all loads of the chunk are issued before the LDS stores
+      constexpr int kIt = kP2PBuf / 64;
+      double4 v[kIt];
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) {
+        const int f = it * 64 + lane;
+        int q = 0;
+#pragma unroll
+        for (int k = 0; k < 15; ++k) q += (__shfl(pre, k) <= f) ? 1 : 0;
+        const int lo = __shfl(pre, q) - __shfl(cnt, q);
+        const int u = __shfl(base, q) + (f - lo);
+        if (f < fill) v[it] = make_double4(px[u], py[u], pz[u], qt[u]);
+      }
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) {
+        const int f = it * 64 + lane;
+        if (f < fill) buf[f] = v[it];
+      }
+      // entries staged completely, and how far into the next one
+      int done = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) done += (k < avail && __shfl(pre, k) <= fill) ? 1 : 0;
+      if (done < avail) {
+        const int prev = done == 0 ? 0 : __shfl(pre, done - 1);
+        off = (done == 0 ? off : 0) + (fill - prev);
+      } else {
+        off = 0;
+      }
+      e += done;
       __syncthreads();
       int u = h;
       for (; u + 3 * R < fill; u += 4 * R) {
-        const double4 a = buf[u], bb = buf[u + R], c = buf[u + 2 * R], d = buf[u + 3 * R];
-        interact(a);
-        interact(bb);
-        interact(c);
-        interact(d);
+        const double4 s0 = buf[u], s1 = buf[u + R], s2 = buf[u + 2 * R], s3 = buf[u + 3 * R];
+        interact(s0);
+        interact(s1);
+        interact(s2);
+        interact(s3);
       }
       for (; u < fill; u += R) interact(buf[u]);
       __syncthreads();
-    };
-    if (near) {
-      int fill = 0;
-      for (int64_t e = e0; e < e1; ++e) {
-        const int j = s_idx[e];
-        int u0 = start[j];
-        const int u1 = start[j + 1];
-        while (u0 < u1) {
-          const int cnt = min(u1 - u0, kP2PBuf - fill);
-          for (int k = lane; k < cnt; k += 64)
-            buf[fill + k] = make_double4(px[u0 + k], py[u0 + k], pz[u0 + k], qt[u0 + k]);
-          fill += cnt;
-          u0 += cnt;
-          if (fill == kP2PBuf) {
-            flush(fill);
-            fill = 0;
-          }
+    }
+    // sum the source streams (fixed order)
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      if (d >= TT) {
+        fa += __shfl_xor(fa, d);
+        gxa += __shfl_xor(gxa, d);
+        gya += __shfl_xor(gya, d);
+        gza += __shfl_xor(gza, d);
+        fb += __shfl_xor(fb, d);
+        gxb += __shfl_xor(gxb, d);
+        gyb += __shfl_xor(gyb, d);
+        gzb += __shfl_xor(gzb, d);
+      }
+    }
+    if (h == 0) {
+      auto put = [&](int t, double f, double gx, double gy, double gz) {
+        if (pout) {
+          pout[t - t0] = make_double4(f, gx, gy, gz);
+          return;
         }
-      }
-      if (fill > 0) flush(fill);
-    }
-    // sum the source splits (fixed order)
-    if (R >= 4) {
-      f += __shfl_xor(f, 16);
-      gx += __shfl_xor(gx, 16);
-      gy += __shfl_xor(gy, 16);
-      gz += __shfl_xor(gz, 16);
-    }
-    if (R >= 2) {
-      f += __shfl_xor(f, 32);
-      gx += __shfl_xor(gx, 32);
-      gy += __shfl_xor(gy, 32);
-      gz += __shfl_xor(gz, 32);
-    }
-    if (valid && h == 0) {
-      if (f0) {
-        f += f0[t];
-        gx += f1[t];
-        gy += f2[t];
-        gz += f3[t];
-      }
-      const int o = perm[t];
-      pot[o] = f;
-      ex[o] = gx;
-      ey[o] = gy;
-      ez[o] = gz;
+        if (f0) {
+          f += f0[t];
+          gx += f1[t];
+          gy += f2[t];
+          gz += f3[t];
+        }
+        const int o = perm[t];
+        pot[o] = f;
+        ex[o] = gx;
+        ey[o] = gy;
+        ez[o] = gz;
+      };
+      if (va) put(ta, fa, gxa, gya, gza);
+      if (vb) put(tb, fb, gxb, gyb, gzb);
     }
   }
 }
 
+// Results of the leaves not written by k_p2p: with partial sums (NEAR = 1)
+// the split leaves, their segments added in order; without the near field
+// (NEAR = 0) every leaf.  One wave per leaf, lanes over targets.
+template <int NEAR>
+__global__ __launch_bounds__(256) void k_p2p_final(int64_t nleaf, const int32_t* __restrict__ start,
+                                                   const int64_t* __restrict__ leaf_seg,
+                                                   const int64_t* __restrict__ leaf_part,
+                                                   const double4* __restrict__ part,
+                                                   const int32_t* __restrict__ perm, const double* __restrict__ f0,
+                                                   const double* __restrict__ f1, const double* __restrict__ f2,
+                                                   const double* __restrict__ f3, double* __restrict__ pot,
+                                                   double* __restrict__ ex, double* __restrict__ ey,
+                                                   double* __restrict__ ez) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= nleaf) return;
+  const int64_t ns = NEAR ? leaf_seg[b + 1] - leaf_seg[b] : 0;
+  if (NEAR && ns <= 1) return;
+  const int t0 = start[b], t1 = start[b + 1], nt = t1 - t0;
+  for (int t = t0 + lane; t < t1; t += 64) {
+    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    if (NEAR) {
+      const double4* pp = part + leaf_part[b] + (t - t0);
+      for (int64_t r = 0; r < ns; ++r) {
+        const double4 v = pp[r * nt];
+        f += v.x;
+        gx += v.y;
+        gy += v.z;
+        gz += v.w;
+      }
+    }
+    if (f0) {
+      f += f0[t];
+      gx += f1[t];
+      gy += f2[t];
+      gz += f3[t];
+    }
+    const int o = perm[t];
+    pot[o] = f;
+    ex[o] = gx;
+    ey[o] = gy;
+    ez[o] = gz;
+  }
+}
+
 }  // namespace
+
+void p2p_plan(Tree& t, hipStream_t s) {
+  const Level& V = t.lev[t.L];
+  const int64_t nleaf = V.nbox;
+  int32_t* nseg = (int32_t*)dalloc(nleaf * sizeof(int32_t), s);
+  int64_t* work = (int64_t*)dalloc(nleaf * sizeof(int64_t), s);
+  int64_t* pcnt = (int64_t*)dalloc(nleaf * sizeof(int64_t), s);
+  unsigned long long* acc = (unsigned long long*)dalloc(sizeof(unsigned long long), s);
+  HIPCHECK(hipMemsetAsync(acc, 0, sizeof(unsigned long long), s));
+  const unsigned gw = (unsigned)((nleaf + 3) / 4);
+  k_seg_plan<false><<<gw, 256, 0, s>>>(nleaf, V.start, V.s_off, V.s_idx, nseg, work, nullptr, nullptr, nullptr);
+  HIPCHECK(hipGetLastError());
+  t.p2p_leaf_seg = (int64_t*)dalloc((nleaf + 1) * sizeof(int64_t), s);
+  t.p2p_leaf_part = (int64_t*)dalloc((nleaf + 1) * sizeof(int64_t), s);
+  scan_counts(nseg, t.p2p_leaf_seg, nleaf, 0, s);
+  k_part_count<<<(unsigned)((nleaf + 255) / 256), 256, 0, s>>>(nleaf, V.start, nseg, pcnt);
+  HIPCHECK(hipGetLastError());
+  scan_counts(pcnt, t.p2p_leaf_part, nleaf, 0, s);
+  k_sum64<<<(unsigned)((nleaf + 255) / 256), 256, 0, s>>>(nleaf, work, acc);
+  HIPCHECK(hipGetLastError());
+  int64_t* h = nullptr;
+  HIPCHECK(hipHostMalloc((void**)&h, 3 * sizeof(int64_t), hipHostMallocDefault));
+  HIPCHECK(hipMemcpyAsync(&h[0], t.p2p_leaf_seg + nleaf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(&h[1], t.p2p_leaf_part + nleaf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(&h[2], acc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  t.p2p_nseg = h[0];
+  t.p2p_npart = h[1];
+  t.p2p_pairs = h[2] - t.n;  // minus the n self pairs
+  HIPCHECK(hipHostFree(h));
+  t.p2p_seg_leaf = (int32_t*)dalloc(std::max<int64_t>(1, t.p2p_nseg) * sizeof(int32_t), s);
+  t.p2p_seg_e0 = (int64_t*)dalloc(std::max<int64_t>(1, t.p2p_nseg) * sizeof(int64_t), s);
+  k_seg_plan<true><<<gw, 256, 0, s>>>(nleaf, V.start, V.s_off, V.s_idx, nullptr, nullptr, t.p2p_leaf_seg,
+                                      t.p2p_seg_leaf, t.p2p_seg_e0);
+  HIPCHECK(hipGetLastError());
+  dfree(nseg, s);
+  dfree(work, s);
+  dfree(pcnt, s);
+  dfree(acc, s);
+}
 
 void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, double* ex, double* ey, double* ez,
               hipStream_t s) {
@@ -181,10 +404,24 @@ void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, dou
   }
   const Level& V = t.lev[L];
   tm.begin(FMM_PH_P2P, s);
-  k_p2p<<<(unsigned)(8 * ((V.nbox + 7) / 8)), 64, 0, s>>>(V.nbox, V.start, V.s_off, V.s_idx, t.px, t.py, t.pz, qt, t.perm,
-                                        (parts & FMM_PART_NEAR) ? 1 : 0, far[0], far[1], far[2], far[3], pot, ex, ey,
-                                        ez);
-  HIPCHECK(hipGetLastError());
+  const unsigned gfin = (unsigned)((V.nbox + 3) / 4);
+  if (parts & FMM_PART_NEAR) {
+    double4* part = t.p2p_npart > 0 ? (double4*)dalloc(t.p2p_npart * sizeof(double4), s) : nullptr;
+    k_p2p<<<(unsigned)(8 * ((t.p2p_nseg + 7) / 8)), 64, 0, s>>>(
+        t.p2p_nseg, t.p2p_seg_leaf, t.p2p_seg_e0, t.p2p_leaf_seg, t.p2p_leaf_part, V.start, V.s_off, V.s_idx, t.px,
+        t.py, t.pz, qt, t.perm, far[0], far[1], far[2], far[3], part, pot, ex, ey, ez);
+    HIPCHECK(hipGetLastError());
+    if (part) {
+      k_p2p_final<1><<<gfin, 256, 0, s>>>(V.nbox, V.start, t.p2p_leaf_seg, t.p2p_leaf_part, part, t.perm, far[0],
+                                         far[1], far[2], far[3], pot, ex, ey, ez);
+      HIPCHECK(hipGetLastError());
+      dfree(part, s);
+    }
+  } else {
+    k_p2p_final<0><<<gfin, 256, 0, s>>>(V.nbox, V.start, nullptr, nullptr, nullptr, t.perm, far[0], far[1], far[2],
+                                       far[3], pot, ex, ey, ez);
+    HIPCHECK(hipGetLastError());
+  }
   tm.end(FMM_PH_P2P, s);
   for (int k = 0; k < 4; ++k)
     if (far[k]) dfree(far[k], s);

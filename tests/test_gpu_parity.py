@@ -119,6 +119,12 @@ def test_parity_full(torch, F, orc, name, gen, n, L, theta, p):
     ot = orc.Tree(x, y, z, L, theta)
     gt = gpu_tree(torch, F, x, y, z, L, theta)
     assert_tree_equal(F, gt, ot, L)
+    # work counts: weak pairs over all levels; near-field interactions
+    n_leaf = np.diff(ot.start(L))
+    so, si = ot.lists(L, 0)
+    src = np.array([n_leaf[si[so[i]:so[i + 1]]].sum() for i in range(n_leaf.size)], dtype=np.int64)
+    m2l_ref = sum(ot.lists(l, 1)[1].size for l in range(1, L + 1))
+    assert F.fmm_tree_stats(gt) == (m2l_ref, int((n_leaf * src).sum()) - n)
     for parts, nm in ((1, "near"), (2, "far"), (3, "all")):
         say(f"[parity] {name}: {nm}")
         ref = ot.evaluate(q, p, parts=parts)
