@@ -391,6 +391,9 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
       for (int t = 0; t < T; ++t) st[t] = *(const d4*)(src + 16 * t);
       wave_lds_fence();
 
+      // the batch body is one basic block; this scheduling strategy
+      // interleaves its matrix and vector instructions better
+      __builtin_amdgcn_iglp_opt(2);
       rotz<P, false, 0>(st, cs_t, 1.0, g, ir);
       japply<P>(st, jf, lane);
       rotz<P, true, 0>(st, cs_a, 1.0, g, ir);  // and (1/rho)^n
