@@ -1,7 +1,7 @@
 // M2L on the matrix cores (Algorithm 3, M2L; rotational form of Section
 // 2.1.3), for expansion orders p <= 15, in FP64 (v_mfma_f64_16x16x4f64).
 //
-// One wave computes the local expansion of one target box i:
+// A block of two waves computes the local expansion of one target box i:
 //   L_i = sum over weak pairs j of  O(Q)^T Z(rho) O(Q) M_j,
 // where Q turns d = c_j - c_i onto the +z axis.  With K the quarter turn
 // about y and J = O(K) (fixed; block-diagonal in the cosine/sine blocks),
@@ -24,7 +24,11 @@
 // lane on (cosine, sine) partners.  For the z translation the coefficients
 // are moved to order-major rows through LDS; per order m it is a fixed
 // matrix (factorials and u folded in) between two diagonal scalings by
-// powers of 1/rho.  The 16 pair results of a batch are summed through LDS
+// powers of 1/rho.  The two waves of a block share each batch: each owns
+// half of the tiles and half of the orders m of the z translation, and they
+// meet at block barriers around the exchanges through LDS; with two such
+// waves on every SIMD, one wave's vector and LDS work runs while the other's
+// matrix products do.  The 16 pair results of a batch are summed through LDS
 // into one accumulator per coefficient: no atomics, deterministic.
 #include "fmm_internal.h"
 #include "tile_layout.h"
@@ -55,22 +59,65 @@ struct Cfg {
   static constexpr int S = tl::stride(P);
   static constexpr int ZR = tl::zrows(P);
   static constexpr int H = tl::hoff(P, P + 1);
-  // z buffer rows: ZR coefficient rows, then a write-only row (also read past
-  // the last order by the zero-padded tail of its last k-step), two more such
-  // rows, and a row that stays zero
+  // z buffer: ZR coefficient rows, a write-only row (also read past the last
+  // order by the zero-padded tail of its last k-step) and two more such rows;
+  // the two waves' pair-sum rounds reuse it
   static constexpr int ZDUMMY = ZR;
-  static constexpr int ZZERO = ZR + 3;
   static constexpr int RSTRIDE = 18;  // row stride of the pair-sum buffer (no bank conflicts)
-  // the pair-sum rounds reuse the z buffer
-  static constexpr int ZBUF = 16 * (ZR + 4) > 64 * RSTRIDE ? 16 * (ZR + 4) : 64 * RSTRIDE;
+  static constexpr int ZBUF = 16 * (ZR + 3) > 2 * 64 * RSTRIDE ? 16 * (ZR + 3) : 2 * 64 * RSTRIDE;
   // per pair: (cos, sin)(m (theta + pi)), (cos, sin)(m (alpha + pi)), m = 0..P;
   // 16 more bytes per pair so that the 16 pair columns hit different banks
   static constexpr int TRIG = 4 * (P + 1) + 2;
-  static constexpr int SHARED = T * 256 + H * 64;
-  static constexpr int PERWAVE = 16 * TRIG + ZBUF;
-  static constexpr int LDS = SHARED + 4 * PERWAVE;
-  static constexpr int NR = (T + 3) / 4;  // pair-sum rounds of four tiles
+  // per block: two trig tables (alternate batches), the z buffer, a row that
+  // stays zero, and the slot that hands out targets
+  static constexpr int LDS = 2 * 16 * TRIG + ZBUF + 16 + 2;
 };
+
+// Work split between the two waves of a block.  Wave 0 owns the degree pairs
+// a < NA (both their cosine and sine tiles) and the mixed tile, wave 1 the
+// other pairs and the two tiles of degree P; the orders m of the z
+// translation go to the wave with the smaller matrix-core load so far.
+template <int P>
+__host__ __device__ constexpr int split_na() {
+  constexpr int NP = tl::npairs(P), MX = tl::has_mixed(P) ? 1 : 0;
+  const int na = (2 * NP + 2 - MX + 2) / 4;
+  return na < NP ? na : NP;
+}
+template <int P>
+__host__ __device__ constexpr int tile_owner(int t) {
+  constexpr int NP = tl::npairs(P);
+  if (t < 2 * NP) return (t < NP ? t : t - NP) < split_na<P>() ? 0 : 1;
+  if (tl::has_mixed(P) && t == tl::mixed_tile(P)) return 0;
+  return 1;
+}
+template <int P>
+__host__ __device__ constexpr int tiles_of(int w) {
+  int c = 0;
+  for (int t = 0; t < tl::ntiles(P); ++t) c += tile_owner<P>(t) == w ? 1 : 0;
+  return c;
+}
+// k-th tile (in tile order) owned by wave w
+template <int P>
+__host__ __device__ constexpr int owned_tile(int w, int k) {
+  for (int t = 0; t < tl::ntiles(P); ++t)
+    if (tile_owner<P>(t) == w && k-- == 0) return t;
+  return 0;
+}
+struct MSplit {
+  int owner[tl::kMaxP + 1];
+};
+template <int P>
+__host__ __device__ constexpr MSplit m_split() {
+  MSplit r{};
+  int load[2] = {16 * tiles_of<P>(0), 16 * tiles_of<P>(1)};  // four J products of four steps per tile
+  // orders by decreasing work: low m first (more rows)
+  for (int m = 0; m <= P; ++m) {
+    const int w = load[0] <= load[1] ? 0 : 1;
+    r.owner[m] = w;
+    load[w] += tl::hsteps(P, m) * (m == 0 ? 1 : 2);
+  }
+  return r;
+}
 
 __device__ __forceinline__ int level_of2(const LevelView& lv, int64_t gid) {
   int l = 0;
@@ -147,17 +194,10 @@ __host__ __device__ constexpr int reg_sine(int t, int i) {
   return t == tl::top_s(P) ? 1 : 0;
 }
 
-// Per-lane views of the small tables.  csg[k] points at (cos, sin) of order
-// k - 4 + g of this lane's pair (k covers the run offsets m0 = -4 .. 15), so
-// the order of a slot is a constant offset; pw[n] = (1/rho)^n.
-struct PairView {
-  const double* csg;
-};
-
 // (c, s) <- f (cos c - sgn sin s, sgn sin c + cos s) for every (cosine, sine)
 // partner pair, f = ir^(n + SHIFT) (SCALE) or 1; cs: this lane's (cos, sin)
 // table shifted by 2 (g - 4)
-template <int P, bool SCALE, int SHIFT>
+template <int P, int W, bool SCALE, int SHIFT>
 __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g, double ir) {
   constexpr int NP = tl::npairs(P);
   double pw[SCALE ? P + 2 : 1];  // (1/rho)^n, built here to keep it short-lived
@@ -187,6 +227,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
   };
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
+    if (tile_owner<P>(a) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       double c = st[a][i], s = st[NP + a][i];
@@ -195,7 +236,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
       st[NP + a][i] = s;
     }
   }
-  if constexpr (tl::has_mixed(P)) {
+  if constexpr (tl::has_mixed(P) && tile_owner<P>(tl::mixed_tile(P)) == W) {
     constexpr int t = tl::mixed_tile(P);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -205,7 +246,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
       st[t][i + 2] = s;
     }
   }
-  {
+  if constexpr (tile_owner<P>(tl::top_c(P)) == W) {
     constexpr int tc = tl::top_c(P), ts = tl::top_s(P);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -217,15 +258,17 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
   }
 }
 
-// st[t] <- J_t st[t] for every tile; jf holds the operand fragments
-template <int P>
-__device__ __forceinline__ void japply(d4* st, const double* jf, int lane) {
+// st[t] <- J_t st[t] for the tiles of wave W; jr: this lane's operand
+// fragments of J (in registers)
+template <int P, int W>
+__device__ __forceinline__ void japply(d4* st, const double* jr) {
   constexpr int T = tl::ntiles(P);
 #pragma unroll
   for (int t = 0; t < T; ++t) {
+    if (tile_owner<P>(t) != W) continue;
     d4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) d = mfma(jf[(t * 4 + k) * 64 + lane], st[t][k], d);
+    for (int k = 0; k < 4; ++k) d = mfma(jr[t * 4 + k], st[t][k], d);
     st[t] = d;
   }
 }
@@ -254,29 +297,33 @@ __device__ __forceinline__ double* zslot(const ZView& z, int t, int i, int g, bo
 
 // z-axis translation of the cosine (SINE = 0) or sine blocks; the input is
 // already scaled by (1/rho)^n and the output by (1/rho)^(j+1) is applied by
-// the next rotation
-template <int P, int SINE>
-__device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol, const double* hf, int lane) {
+// the next rotation.  Both waves move their tiles to the order-major rows
+// and back; each computes its own orders.  hr: this lane's operand fragments
+// of the order-m matrices (in registers).
+template <int P, int W, int SINE>
+__device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol, const double* hr, int lane) {
   constexpr int T = tl::ntiles(P);
+  constexpr MSplit ms = m_split<P>();
   const int g = lane >> 4;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
+    if (tile_owner<P>(t) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE) continue;
       *zslot<P>(z, t, i, g, false) = st[t][i];
     }
   }
-  wave_lds_fence();
-  // zcol: this lane's column at row g
+  __syncthreads();
 #pragma unroll
   for (int m = SINE; m <= P; ++m) {
+    if (ms.owner[m] != W) continue;
     const int K = P + 1 - m;
     const int zo = tl::zoff(P, m);
     const int ho = tl::hoff(P, m);
     d4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < tl::hsteps(P, m); ++k) d = mfma(hf[(ho + k) * 64 + lane], zcol[(zo + 4 * k) * 16], d);
+    for (int k = 0; k < tl::hsteps(P, m); ++k) d = mfma(hr[ho + k], zcol[(zo + 4 * k) * 16], d);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (4 * i >= K) continue;
@@ -284,41 +331,53 @@ __device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol
       *dst = d[i];
     }
   }
-  wave_lds_fence();
+  __syncthreads();
 #pragma unroll
   for (int t = 0; t < T; ++t) {
+    if (tile_owner<P>(t) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE) continue;
       st[t][i] = *zslot<P>(z, t, i, g, true);
     }
   }
-  wave_lds_fence();
+  __syncthreads();
 }
 
-template <int P>
-__global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double* __restrict__ mtab,
-                                                     const double* __restrict__ Mx, double* __restrict__ Lx,
-                                                     int64_t ntarget, const int32_t* __restrict__ order,
-                                                     int* __restrict__ queue) {
+// the work of wave W of the block (both waves run the same loop structure
+// and meet at the same barriers)
+template <int P, int W>
+__device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, const double* __restrict__ mtab,
+                                         const double* __restrict__ Mx, double* __restrict__ Lx, int64_t ntarget,
+                                         const int32_t* __restrict__ order, int* __restrict__ queue) {
   using C = Cfg<P>;
   constexpr int T = C::T;
   constexpr int S = C::S;
-  __shared__ double smem[C::LDS];
-  const double* jf = smem;
-  const double* hf = smem + T * 256;
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int NTW = tiles_of<P>(W);
+  constexpr int NRW = (NTW + 3) / 4;  // pair-sum rounds of four tiles
+  constexpr MSplit ms = m_split<P>();
+  const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, g = lane >> 4;
-  double* trig = smem + C::SHARED + wid * C::PERWAVE;
-  double* zb = trig + 16 * C::TRIG;
-  // every LDS word starts finite: buffer tails are read (and multiplied by 0)
-  for (int k = threadIdx.x; k < C::LDS; k += 256) smem[k] = k < C::SHARED ? mtab[k] : 0.0;
-  __syncthreads();
+  double* trig = smem;                       // two tables, alternate batches
+  double* zb = smem + 2 * 16 * C::TRIG;
+  double* zero_row = zb + C::ZBUF;           // stays zero
+  int* slot = (int*)(zero_row + 16);         // target handed to the block
 
-  double* tp = trig + r16 * C::TRIG;  // this lane's pair
-  // (cos, sin) tables shifted so that entry 2 (m0 + 4) is order m0 + g
-  const double* cs_t = tp + 2 * (g - 4);
-  const double* cs_a = tp + 2 * (P + 1) + 2 * (g - 4);
+  // operand fragments of this wave's J tiles and orders, kept in registers
+  double jr[T * 4];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+    if (tile_owner<P>(t) == W)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) jr[t * 4 + k] = mtab[(t * 4 + k) * 64 + lane];
+  double hr[C::H];
+#pragma unroll
+  for (int m = 0; m <= P; ++m)
+    if (ms.owner[m] == W)
+#pragma unroll
+      for (int k = 0; k < tl::hsteps(P, m); ++k)
+        hr[tl::hoff(P, m) + k] = mtab[T * 256 + (tl::hoff(P, m) + k) * 64 + lane];
+
   ZView z;
 #pragma unroll
   for (int k = 0; k < 20; ++k) {
@@ -326,15 +385,17 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
     z.zl[k] = zb + 16 * (tl::zoff(P, m) - m) + r16;
   }
   z.zd = zb + 16 * C::ZDUMMY + r16;
-  z.zz = zb + 16 * C::ZZERO + r16;
+  z.zz = zero_row + r16;
   double* zcol = zb + 16 * g + r16;
+  double* red = zb + W * 64 * C::RSTRIDE;  // this wave's pair-sum rows
 
-  // persistent waves: each takes the next target of the longest-first order
-  // until the queue is empty (no block-wide barrier below this point)
+  // persistent blocks: each takes the next target of the longest-first order
+  // until the queue is empty
   for (;;) {
-    int k_next = 0;
-    if (lane == 0) k_next = atomicAdd(queue, 1);
-    k_next = __shfl(k_next, 0);
+    if (W == 0 && lane == 0) *slot = atomicAdd(queue, 1);
+    __syncthreads();
+    const int k_next = *slot;
+    __syncthreads();
     if (k_next >= ntarget) break;
     const int64_t tgt = order[k_next];
     const int64_t gid = lv.gofs[1] + tgt;
@@ -346,11 +407,12 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
     const int32_t* widx = lv.w_idx[l];
     const double* Mlev = Mx + (size_t)lv.gofs[l] * S;
 
-    double acc[C::NR];
+    double acc[NRW > 0 ? NRW : 1];
 #pragma unroll
-    for (int r = 0; r < C::NR; ++r) acc[r] = 0.0;
+    for (int r = 0; r < NRW; ++r) acc[r] = 0.0;
 
-    for (int64_t eb = e0; eb < e1; eb += 16) {
+    int buf = 0;
+    for (int64_t eb = e0; eb < e1; eb += 16, buf ^= 1) {
       // pair of this lane's column; past the end of the list the column
       // repeats the first source with 1/rho = 0, which zeroes its result
       const int64_t e = eb + r16;
@@ -366,16 +428,22 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
       const double rxy2 = dx * dx + dy * dy;
       const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
       const double irho = 1.0 / rho;
-      const double irxy = rxy > 0.0 ? 1.0 / rxy : 0.0;
       const double ir = valid ? irho : 0.0;
-      // (cos, sin)(m (angle + pi)) by the angle-addition recurrence; lane
-      // groups 0, 2 build the theta table and 1, 3 the alpha table (groups 2
-      // and 3 write the same values to the same words as 0 and 1)
+      double* tp = trig + buf * 16 * C::TRIG + r16 * C::TRIG;  // this lane's pair
+      // (cos, sin)(m (angle + pi)) by the angle-addition recurrence: wave 0
+      // builds the theta table, wave 1 the alpha table (the four lane groups
+      // write the same values to the same words)
       {
-        const bool ta = (g & 1) != 0;
-        const double c1 = ta ? -dz * irho : -dy * irxy;
-        const double s1 = ta ? -rxy * irho : (rxy > 0.0 ? -dx * irxy : -1.0);
-        double* dst = tp + (ta ? 2 * (P + 1) : 0);
+        double c1, s1;
+        if (W == 0) {
+          const double irxy = rxy > 0.0 ? 1.0 / rxy : 0.0;
+          c1 = -dy * irxy;
+          s1 = rxy > 0.0 ? -dx * irxy : -1.0;
+        } else {
+          c1 = -dz * irho;
+          s1 = -rxy * irho;
+        }
+        double* dst = tp + (W == 0 ? 0 : 2 * (P + 1));
         double c = 1.0, s = 0.0;
 #pragma unroll
         for (int m = 0; m <= P; ++m) {
@@ -388,37 +456,38 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
       d4 st[T];
       const double* src = Mlev + (size_t)j * S + 4 * g;
 #pragma unroll
-      for (int t = 0; t < T; ++t) st[t] = *(const d4*)(src + 16 * t);
-      wave_lds_fence();
+      for (int t = 0; t < T; ++t)
+        if (tile_owner<P>(t) == W) st[t] = *(const d4*)(src + 16 * t);
+      __syncthreads();  // both tables written
 
-      // the batch body is one basic block; this scheduling strategy
-      // interleaves its matrix and vector instructions better
-      __builtin_amdgcn_iglp_opt(2);
-      rotz<P, false, 0>(st, cs_t, 1.0, g, ir);
-      japply<P>(st, jf, lane);
-      rotz<P, true, 0>(st, cs_a, 1.0, g, ir);  // and (1/rho)^n
-      japply<P>(st, jf, lane);
-      ztrans_part<P, 0>(st, z, zcol, hf, lane);
-      ztrans_part<P, 1>(st, z, zcol, hf, lane);
-      japply<P>(st, jf, lane);
-      rotz<P, true, 1>(st, cs_a, -1.0, g, ir);  // and (1/rho)^(j+1)
-      japply<P>(st, jf, lane);
-      rotz<P, false, 0>(st, cs_t, -1.0, g, ir);
+      // (cos, sin) tables shifted so that entry 2 (m0 + 4) is order m0 + g
+      const double* cs_t = tp + 2 * (g - 4);
+      const double* cs_a = tp + 2 * (P + 1) + 2 * (g - 4);
+      rotz<P, W, false, 0>(st, cs_t, 1.0, g, ir);
+      japply<P, W>(st, jr);
+      rotz<P, W, true, 0>(st, cs_a, 1.0, g, ir);  // and (1/rho)^n
+      japply<P, W>(st, jr);
+      ztrans_part<P, W, 0>(st, z, zcol, hr, lane);
+      ztrans_part<P, W, 1>(st, z, zcol, hr, lane);
+      japply<P, W>(st, jr);
+      rotz<P, W, true, 1>(st, cs_a, -1.0, g, ir);  // and (1/rho)^(j+1)
+      japply<P, W>(st, jr);
+      rotz<P, W, false, 0>(st, cs_t, -1.0, g, ir);
 
-      // sum over the 16 pairs: four tiles per round through LDS; lane L adds
-      // up row L (slot L % 16 of tile 4 r + L / 16)
+      // sum over the 16 pairs, four of this wave's tiles per round; lane L
+      // adds up row L (slot L % 16 of its tile 4 r + L / 16)
 #pragma unroll
-      for (int r = 0; r < C::NR; ++r) {
+      for (int r = 0; r < NRW; ++r) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int t = 4 * r + q;
-          if (t >= T) continue;
+          if (4 * r + q >= NTW) continue;
+          const int t = owned_tile<P>(W, 4 * r + q);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) zb[(q * 16 + 4 * i + g) * C::RSTRIDE + r16] = st[t][i];
+          for (int i = 0; i < 4; ++i) red[(q * 16 + 4 * i + g) * C::RSTRIDE + r16] = st[t][i];
         }
         wave_lds_fence();
-        if (4 * r + 3 < T || 4 * r + (lane >> 4) < T) {
-          const double* row = zb + lane * C::RSTRIDE;
+        if (4 * r + 3 < NTW || 4 * r + (lane >> 4) < NTW) {
+          const double* row = red + lane * C::RSTRIDE;
           d2 v = *(const d2*)row;
 #pragma unroll
           for (int k = 1; k < 8; ++k) v += *(const d2*)(row + 2 * k);
@@ -427,18 +496,33 @@ __global__ __launch_bounds__(256, 1) void k_m2l_mfma(LevelView lv, const double*
         wave_lds_fence();
       }
     }
-    // lane L holds slot L % 16 of tile 4 r + L / 16; the final D is the
-    // sign (-1)^m
+    // lane L holds slot L % 16 of the wave's tile 4 r + L / 16; the final D is
+    // the sign (-1)^m
     double* dst = Lx + (size_t)gid * S;
 #pragma unroll
-    for (int r = 0; r < C::NR; ++r) {
-      const int t = 4 * r + (lane >> 4);
-      if (t < T) {
+    for (int r = 0; r < NRW; ++r) {
+      const int k = 4 * r + (lane >> 4);
+      if (k < NTW) {
+        const int t = owned_tile<P>(W, k);
         const Pos d = slot_pos<P>(t, lane & 15);
         dst[tl::spos(t, lane & 15)] = (d.m & 1) ? -acc[r] : acc[r];
       }
     }
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_m2l_mfma(
+    LevelView lv, const double* __restrict__ mtab, const double* __restrict__ Mx, double* __restrict__ Lx,
+    int64_t ntarget, const int32_t* __restrict__ order, int* __restrict__ queue) {
+  __shared__ double smem[Cfg<P>::LDS];
+  // every LDS word starts finite: buffer tails are read (and multiplied by 0)
+  for (int k = threadIdx.x; k < Cfg<P>::LDS; k += 128) smem[k] = 0.0;
+  __syncthreads();
+  if (threadIdx.x < 64)
+    m2l_wave<P, 0>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
+  else
+    m2l_wave<P, 1>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
 }
 
 template <int P>
@@ -449,14 +533,14 @@ void launch_one(const Tree& t, const Tables& tb, const double* Mx, double* Lx, h
     int dev = 0, ncu = 0, per = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P>, 256, 0));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P>, 128, 0));
     grid_max = ncu * (per > 0 ? per : 1);
   }
-  const int64_t need = (ntarget + 3) / 4;
+  const int64_t need = ntarget;
   const unsigned grid = (unsigned)(need < grid_max ? need : grid_max);
   int* queue = (int*)dalloc(sizeof(int), s);
   HIPCHECK(hipMemsetAsync(queue, 0, sizeof(int), s));
-  k_m2l_mfma<P><<<grid, 256, 0, s>>>(t.view(), tb.mtab, Mx, Lx, ntarget, t.m2l_order, queue);
+  k_m2l_mfma<P><<<grid, 128, 0, s>>>(t.view(), tb.mtab, Mx, Lx, ntarget, t.m2l_order, queue);
   HIPCHECK(hipGetLastError());
   dfree(queue, s);
 }
