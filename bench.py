@@ -6,6 +6,8 @@ theta 0.5, p 15, FP64), with inputs and outputs resident in HBM.  Prints one
 JSON line.  `value` = points per second of the whole step.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+    python bench.py --copy-bytes N   (one device-to-device copy of N bytes, for
+                                      calibrating the HBM traffic counters)
 """
 from __future__ import annotations
 
@@ -24,6 +26,40 @@ from paper_2002_04894_amd import fmm, workloads  # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (and matrix) peak
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of one M2L launch on the 2^20-point mixture (p 15), from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) of
+# `bench.py --steps 1 --warmup 0 --no-cpu`, scaled by the same counters on a
+# 1 GiB device copy (`bench.py --copy-bytes 1073741824`): FETCH_SIZE read
+# 524308 KiB and WRITE_SIZE 1048576 KiB for 1048576 KiB moved each way.
+# Valid only for the kernel source it was taken on (hash below).
+M2L_COUNTERS = {
+    "sources_sha256": "0263b1be87a6bbc34e7f9be92b919363291b2708959e92776b3ea0574ea6f3c9",
+    "workload": "gmix1m",
+    "fetch_kib": 155111634.0,
+    "write_kib": 1056946.5,
+    "fetch_scale": 1048576.0 / 524308.375,
+    "write_scale": 1.0,
+}
+
+
+def m2l_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("m2l_mfma.hip", "tile_layout.h"):
+        with open(os.path.join(ROOT, "paper_2002_04894_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def m2l_traffic_gb(workload: str):
+    """HBM bytes (GB) per M2L launch from the counters above, or None when
+    they were taken on another workload or another version of the kernel."""
+    c = M2L_COUNTERS
+    if workload != c["workload"] or m2l_sources_sha256() != c["sources_sha256"]:
+        return None
+    kib = c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]
+    return round(kib * 1024 / 1e9, 2)
 
 
 def m2l_flops_per_pair(p: int) -> int:
@@ -47,7 +83,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gmix1m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        copy_probe(args.copy_bytes)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -105,7 +146,8 @@ def main():
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": m2l_traffic_gb(args.workload),
+        "traffic_unit": "GB per launch",
         "launch_ms": round(m2l_ms, 4),
         "pairs": int(m2l_pairs),
         "flops_per_pair": m2l_flops_per_pair(p),
@@ -139,6 +181,19 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w)
         line["accuracy"] = accuracy_gate(x, y, z, q, outs)
     print(json.dumps(line), flush=True)
+
+
+def copy_probe(nbytes: int):
+    """One device-to-device copy of `nbytes` (after one untimed warm-up copy),
+    whose FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 8}), flush=True)
 
 
 def cpu_baseline(w):
