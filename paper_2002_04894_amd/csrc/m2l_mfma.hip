@@ -463,12 +463,15 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
       // (cos, sin) tables shifted so that entry 2 (m0 + 4) is order m0 + g
       const double* cs_t = tp + 2 * (g - 4);
       const double* cs_a = tp + 2 * (P + 1) + 2 * (g - 4);
+      // scheduling strategy for the long barrier-free stretches
+      __builtin_amdgcn_iglp_opt(0);
       rotz<P, W, false, 0>(st, cs_t, 1.0, g, ir);
       japply<P, W>(st, jr);
       rotz<P, W, true, 0>(st, cs_a, 1.0, g, ir);  // and (1/rho)^n
       japply<P, W>(st, jr);
       ztrans_part<P, W, 0>(st, z, zcol, hr, lane);
       ztrans_part<P, W, 1>(st, z, zcol, hr, lane);
+      __builtin_amdgcn_iglp_opt(0);
       japply<P, W>(st, jr);
       rotz<P, W, true, 1>(st, cs_a, -1.0, g, ir);  // and (1/rho)^(j+1)
       japply<P, W>(st, jr);
