@@ -34,10 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # 524308 KiB and WRITE_SIZE 1048576 KiB for 1048576 KiB moved each way.
 # Valid only for the kernel source it was taken on (hash below).
 M2L_COUNTERS = {
-    "sources_sha256": "0263b1be87a6bbc34e7f9be92b919363291b2708959e92776b3ea0574ea6f3c9",
+    "sources_sha256": "3f15f5b0b5b205291b174b96bfc449a0c322a8ef7ca32d3a1a3b3c01841dc782",
     "workload": "gmix1m",
-    "fetch_kib": 155111634.0,
-    "write_kib": 1056946.5,
+    "fetch_kib": 136356624.9375,
+    "write_kib": 9581895.5,
     "fetch_scale": 1048576.0 / 524308.375,
     "write_scale": 1.0,
 }
