@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gmix1m")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="steps of the mixed-precision mode timed after the binary64 ones (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -103,9 +105,9 @@ def main():
     outs = [torch.empty_like(X) for _ in range(4)]
     stream = torch.cuda.current_stream()
 
-    def step():
+    def step(outs=outs, precision=fmm.FMM_PREC_F64):
         t = fmm.fmm_build(X, Y, Z, L, theta, stream)
-        fmm.fmm_evaluate_tree(t, Q, p, *outs, stream)
+        fmm.fmm_evaluate_tree(t, Q, p, *outs, stream, precision=precision)
         return t
 
     fmm.fmm_set_profiling(True)
@@ -177,10 +179,45 @@ def main():
         "wall_s": round(wall, 3),
     }
 
+    mouts = None
+    if args.mixed_steps > 0:
+        mouts = [torch.empty_like(X) for _ in range(4)]
+        line["mixed"] = mixed_leg(step, mouts, outs, n, args.mixed_steps, stream, torch)
+
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w)
         line["accuracy"] = accuracy_gate(x, y, z, q, outs)
+        if mouts is not None:
+            line["mixed"]["accuracy"] = accuracy_gate(x, y, z, q, mouts)
     print(json.dumps(line), flush=True)
+
+
+def mixed_leg(step, mouts, outs, n, steps, stream, torch):
+    """The same step in mixed precision (binary32 M2L, the rest binary64):
+    one warm-up and `steps` timed steps, its M2L time, and its difference to
+    the binary64 result just computed (normwise, potential and field)."""
+    step(mouts, fmm.FMM_PREC_MIXED).free()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    m2l = 0.0
+    e0.record(stream)
+    last = None
+    for _ in range(steps):
+        tr = step(mouts, fmm.FMM_PREC_MIXED)
+        m2l += fmm.fmm_last_timings()["m2l"]
+        if last is not None:
+            last.free()
+        last = tr
+    e1.record(stream)
+    torch.cuda.synchronize()
+    last.free()
+    ms = e0.elapsed_time(e1) / steps
+    dphi = float(torch.linalg.norm(mouts[0] - outs[0]) / torch.linalg.norm(outs[0]))
+    dE = float(torch.sqrt(sum(torch.sum((a - b) ** 2) for a, b in zip(mouts[1:], outs[1:])))
+               / torch.sqrt(sum(torch.sum(b ** 2) for b in outs[1:])))
+    return {"dtype": "f32 m2l, f64 rest", "steps": steps, "ms_per_step": round(ms, 4),
+            "value": round(n / (ms * 1e-3), 1), "unit": "points/s", "m2l_ms": round(m2l / steps, 4),
+            "rel_diff_vs_f64": {"phi": dphi, "E": dE}}
 
 
 def copy_probe(nbytes: int):

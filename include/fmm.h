@@ -85,6 +85,26 @@ int fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, doubl
 int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
                             double* ez, void* stream);
 
+/* Arithmetic of the evaluation (fmm_evaluate_tree_ex). */
+#define FMM_PREC_F64 0   /* every step in IEEE binary64 */
+#define FMM_PREC_MIXED 1 /* M2L in binary32 (see below); the rest in binary64 */
+
+/*
+ * As fmm_evaluate_tree_parts, with a choice of arithmetic.  FMM_PREC_MIXED
+ * evaluates the dominant M2L step (Section 2.1.3) in binary32 for orders
+ * p <= 15: the multipoles are scaled by powers of their box radius, so that
+ * every translation factor (r_source/rho)^n, (r_target/rho)^j is below one;
+ * the rotations and the z-axis translation run on the binary32 matrix cores;
+ * the 16 pairs of a batch are summed in binary32 and the batches in binary64;
+ * the local expansions are unscaled into binary64.  The tree, P2M, M2M, L2L,
+ * L2P and the near field (P2P) stay in binary64, as do all final sums.  The
+ * far field then differs from the binary64 one by about 1e-7 relative
+ * (normwise) on the workloads tested.  Higher orders run in binary64.
+ * Returns FMM_EINVAL for an unknown precision.
+ */
+int fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+                         double* ey, double* ez, void* stream);
+
 /* One-shot form: fmm_build + fmm_evaluate_tree + fmm_free.  All arrays are
  * device arrays of n doubles. */
 int fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,

@@ -238,15 +238,21 @@ int fmm_build(const double* x, const double* y, const double* z, int64_t n, int 
   });
 }
 
-int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
-                            double* ez, void* stream) {
+int fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+                         double* ey, double* ez, void* stream) {
   return fmm::guarded([&] {
     fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
     validate_eval_args(q, p, pot, ex, ey, ez);
     if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
     t.stream = (hipStream_t)stream;
-    fmm::evaluate(t, q, p, parts, pot, ex, ey, ez, (hipStream_t)stream);
+    fmm::evaluate(t, q, p, parts, precision, pot, ex, ey, ez, (hipStream_t)stream);
   });
+}
+
+int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
+                            double* ez, void* stream) {
+  return fmm_evaluate_tree_ex(tree, q, p, parts, FMM_PREC_F64, pot, ex, ey, ez, stream);
 }
 
 int fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, double* ex, double* ey, double* ez,
@@ -263,7 +269,7 @@ int fmm_evaluate(const double* x, const double* y, const double* z, const double
     hipStream_t s = (hipStream_t)stream;
     fmm_tree* h = build_impl(x, y, z, n, levels, theta, s);
     try {
-      fmm::evaluate(h->t, q, p, FMM_PART_ALL, pot, ex, ey, ez, s);
+      fmm::evaluate(h->t, q, p, FMM_PART_ALL, FMM_PREC_F64, pot, ex, ey, ez, s);
     } catch (...) {
       fmm::release(h->t);
       delete h;

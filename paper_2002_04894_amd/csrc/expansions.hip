@@ -121,7 +121,9 @@ int parity_class(int i) {
 
 struct HostTables {
   std::vector<double> J, A, B, rc, mtab;
+  std::vector<float> mtab32;
   std::vector<int> joff, pos, ipos;
+  std::vector<int8_t> sdeg;
   int stride = 0;
   bool tiled = false;
 };
@@ -223,6 +225,7 @@ HostTables make_host_tables(int p) {
     for (int k = 0; k < nt; ++k) h.pos[k] = h.ipos[k] = k;
     return h;
   }
+  h.sdeg.assign(h.stride, -1);
   for (int t = 0; t < tl::ntiles(p); ++t)
     for (int sl = 0; sl < 16; ++sl) {
       const tl::Slot d = tl::decode(p, t, sl);
@@ -230,6 +233,7 @@ HostTables make_host_tables(int p) {
       const int k = d.n * d.n + (d.m == 0 ? 0 : 2 * d.m - 1 + d.sine);
       h.pos[k] = tl::spos(t, sl);
       h.ipos[tl::spos(t, sl)] = k;
+      h.sdeg[tl::spos(t, sl)] = (int8_t)d.n;
     }
   // MFMA tables, stored as operand fragments (entry [step][lane] is what lane
   // `lane` feeds to the k-step `step` of a 16x16x4 chain: row lane % 16,
@@ -270,6 +274,17 @@ HostTables make_host_tables(int p) {
         hf[((size_t)tl::hoff(p, m) + st) * 64 + lane] = (double)(sg * f_all(2 * m + a + b) * u);
       }
   }
+  // binary32 fragments for v_mfma_f32_16x16x4f32, whose result rows are
+  // 4 (lane / 16) + i (against 4 i + lane / 16 for the binary64 one): the
+  // same fragments with the operand row r read from row 4 (r % 4) + r / 4,
+  // so that the binary32 chains see the same slot order as the binary64 ones
+  h.mtab32.resize(h.mtab.size());
+  const size_t nfrag = h.mtab.size() / 64;
+  for (size_t f = 0; f < nfrag; ++f)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int r = lane % 16, src_lane = (4 * (r % 4) + r / 4) + 16 * (lane / 16);
+      h.mtab32[f * 64 + lane] = (float)h.mtab[f * 64 + src_lane];
+    }
   return h;
 }
 
@@ -305,7 +320,11 @@ const Tables& tables_for(int p, hipStream_t) {
   t.pos = upload(h.pos);
   t.ipos = upload(h.ipos);
   t.tiled = h.tiled;
-  if (h.tiled) t.mtab = upload(h.mtab);
+  if (h.tiled) {
+    t.mtab = upload(h.mtab);
+    t.mtab32 = upload(h.mtab32);
+    t.sdeg = upload(h.sdeg);
+  }
   return g_tabs.emplace(std::make_pair(dev, p), t).first->second;
 }
 
@@ -725,9 +744,12 @@ void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t 
   HIPCHECK(hipGetLastError());
 }
 bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
+bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
 
-void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
-  if (launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
+// M2L on the matrix cores for p <= 15 (binary64, or binary32 on scaled
+// expansions for FMM_PREC_MIXED), else the binary64 kernel above
+void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, int prec, hipStream_t s) {
+  if (prec == FMM_PREC_MIXED ? launch_m2l_mfma_mixed(t, tb, Mx, Lx, s) : launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
   const int64_t nb = t.nbox_total - 1;  // levels 1..L
   k_m2l<<<(unsigned)nb, 64, 0, s>>>(t.view(), make_xt(tb), Mx, Lx);
   HIPCHECK(hipGetLastError());

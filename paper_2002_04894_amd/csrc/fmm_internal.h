@@ -97,9 +97,12 @@ struct Tables {
   int stride = 0;
   int* pos = nullptr;
   int* ipos = nullptr;
-  // MFMA translation tables (p <= 15): y-quarter-turn tile matrices
-  // [ntiles][16][17], factorials [32], 1/sqrt((n+m)!(n-m)!) at [16*m + n]
+  // MFMA translation tables (p <= 15), as operand fragments [step][lane]:
+  // the y-quarter-turn tile matrices [ntiles * 4][64], then the z-translation
+  // matrices per order [sum_m hsteps][64]
   double* mtab = nullptr;
+  float* mtab32 = nullptr;  // the same in binary32, rows ordered for the binary32 MFMA
+  int8_t* sdeg = nullptr;  // degree of each storage position, -1 for a zero slot
   bool tiled = false;
 };
 const Tables& tables_for(int p, hipStream_t s);
@@ -116,7 +119,7 @@ PhaseTimer& timer();
 void tree_build(Tree& t, const double* x, const double* y, const double* z, hipStream_t s);
 void lists_build(Tree& t, hipStream_t s);
 void p2p_plan(Tree& t, hipStream_t s);
-void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, double* ex, double* ey, double* ez,
+void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey, double* ez,
               hipStream_t s);
 
 // exclusive scan of int32 counts into int64 offsets (out[n] = total + base)

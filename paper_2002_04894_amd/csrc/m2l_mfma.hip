@@ -38,6 +38,25 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+// The kernel runs in binary64, or (mixed precision) in binary32 on
+// radius-scaled expansions: R is the arithmetic type of the translations.
+template <class R>
+struct Ar;
+template <>
+struct Ar<double> {
+  typedef d4 v4;
+  typedef d2 v2;
+  static constexpr int kRowStride = 18;  // pair-sum rows: 144 B, no bank conflicts
+};
+template <>
+struct Ar<float> {
+  typedef f4 v4;
+  typedef f2 v2;
+  static constexpr int kRowStride = 20;
+};
 
 // Orders this wave's LDS accesses around a point (other lanes of the wave
 // read what this lane wrote): a compiler barrier only, since the LDS unit
@@ -51,8 +70,11 @@ __device__ __forceinline__ void wave_lds_fence() {
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
-template <int P>
+template <int P, class R>
 struct Cfg {
   static constexpr int T = tl::ntiles(P);
   static constexpr int NP = tl::npairs(P);
@@ -63,13 +85,13 @@ struct Cfg {
   // order by the zero-padded tail of its last k-step) and two more such rows;
   // the two waves' pair-sum rounds reuse it
   static constexpr int ZDUMMY = ZR;
-  static constexpr int RSTRIDE = 18;  // row stride of the pair-sum buffer (no bank conflicts)
+  static constexpr int RSTRIDE = Ar<R>::kRowStride;
   static constexpr int ZBUF = 16 * (ZR + 3) > 2 * 64 * RSTRIDE ? 16 * (ZR + 3) : 2 * 64 * RSTRIDE;
   // per pair: (cos, sin)(m (theta + pi)), (cos, sin)(m (alpha + pi)), m = 0..P;
   // 16 more bytes per pair so that the 16 pair columns hit different banks
   static constexpr int TRIG = 4 * (P + 1) + 2;
   // per block: two trig tables (alternate batches), the z buffer, a row that
-  // stays zero, and the slot that hands out targets
+  // stays zero, and the slot that hands out targets (elements of R)
   static constexpr int LDS = 2 * 16 * TRIG + ZBUF + 16 + 2;
 };
 
@@ -195,33 +217,33 @@ __host__ __device__ constexpr int reg_sine(int t, int i) {
 }
 
 // (c, s) <- f (cos c - sgn sin s, sgn sin c + cos s) for every (cosine, sine)
-// partner pair, f = ir^(n + SHIFT) (SCALE) or 1; cs: this lane's (cos, sin)
-// table shifted by 2 (g - 4)
-template <int P, int W, bool SCALE, int SHIFT>
-__device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g, double ir) {
+// partner pair, f = mult * base^n for a slot of degree n (SCALE) or 1; cs:
+// this lane's (cos, sin) table shifted by 2 (g - 4)
+template <int P, int W, bool SCALE, class R>
+__device__ __forceinline__ void rotz(typename Ar<R>::v4* st, const R* cs, R sgn, int g, R base, R mult) {
+  typedef typename Ar<R>::v2 v2;
   constexpr int NP = tl::npairs(P);
-  double pw[SCALE ? P + 2 : 1];  // (1/rho)^n, built here to keep it short-lived
-  pw[0] = 1.0;
+  R pw[SCALE ? P + 1 : 1];  // mult * base^n, built here to keep it short-lived
+  pw[0] = mult;
   if constexpr (SCALE) {
 #pragma unroll
-    for (int n = 1; n <= P + 1; ++n) pw[n] = pw[n - 1] * ir;
+    for (int n = 1; n <= P; ++n) pw[n] = pw[n - 1] * base;
   }
-  auto rot = [&](double& c, double& s, int t, int i) {
+  auto rot = [&](R& c, R& s, int t, int i) {
     const Quad q = quad<P>(t, i);
     const int k0 = 2 * (q.m0[0] + 4), k1 = 2 * (q.m0[1] + 4), k2 = 2 * (q.m0[2] + 4);
     // a padding run reads any finite entry: its coefficients are zero
-    const d2 v = *(const d2*)(cs + pick(q, g, q.pad[0] ? 8 : k0, q.pad[1] ? 8 : k1, q.pad[2] ? 8 : k2));
-    double co = v.x, si = sgn * v.y;
+    const v2 v = *(const v2*)(cs + pick(q, g, q.pad[0] ? 8 : k0, q.pad[1] ? 8 : k1, q.pad[2] ? 8 : k2));
+    R co = v.x, si = sgn * v.y;
     if constexpr (SCALE) {
-      const double f = q.nseg == 1 ? pw[q.n[0] + SHIFT]
-                                   : (g < q.end[0] ? pw[q.n[0] + SHIFT]
-                                                   : (q.nseg == 2 || g < q.end[1] ? pw[q.n[1] + SHIFT]
-                                                                                 : pw[q.n[2] + SHIFT]));
+      const R f = q.nseg == 1 ? pw[q.n[0]]
+                              : (g < q.end[0] ? pw[q.n[0]]
+                                              : (q.nseg == 2 || g < q.end[1] ? pw[q.n[1]] : pw[q.n[2]]));
       co *= f;
       si *= f;
     }
-    const double nc = co * c - si * s;
-    const double ns = si * c + co * s;
+    const R nc = co * c - si * s;
+    const R ns = si * c + co * s;
     c = nc;
     s = ns;
   };
@@ -230,7 +252,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
     if (tile_owner<P>(a) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      double c = st[a][i], s = st[NP + a][i];
+      R c = st[a][i], s = st[NP + a][i];
       rot(c, s, a, i);
       st[a][i] = c;
       st[NP + a][i] = s;
@@ -240,7 +262,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
     constexpr int t = tl::mixed_tile(P);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      double c = st[t][i], s = st[t][i + 2];
+      R c = st[t][i], s = st[t][i + 2];
       rot(c, s, t, i);
       st[t][i] = c;
       st[t][i + 2] = s;
@@ -250,7 +272,7 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
     constexpr int tc = tl::top_c(P), ts = tl::top_s(P);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      double c = st[tc][i], s = st[ts][i];
+      R c = st[tc][i], s = st[ts][i];
       rot(c, s, tc, i);
       st[tc][i] = c;
       st[ts][i] = s;
@@ -260,13 +282,13 @@ __device__ __forceinline__ void rotz(d4* st, const double* cs, double sgn, int g
 
 // st[t] <- J_t st[t] for the tiles of wave W; jr: this lane's operand
 // fragments of J (in registers)
-template <int P, int W>
-__device__ __forceinline__ void japply(d4* st, const double* jr) {
+template <int P, int W, class R>
+__device__ __forceinline__ void japply(typename Ar<R>::v4* st, const R* jr) {
   constexpr int T = tl::ntiles(P);
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     if (tile_owner<P>(t) != W) continue;
-    d4 d = {0.0, 0.0, 0.0, 0.0};
+    typename Ar<R>::v4 d = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) d = mfma(jr[t * 4 + k], st[t][k], d);
     st[t] = d;
@@ -276,22 +298,23 @@ __device__ __forceinline__ void japply(d4* st, const double* jr) {
 // z buffer addressing: zl[k] points at row zoff(m) - m of this lane's column
 // for m = k - 4 + g (so that row (m, n) is zl[k] + 16 n), zd at the
 // write-only row, zz at the zero row
+template <class R>
 struct ZView {
-  double* zl[20];
-  double* zd;
-  const double* zz;
+  R* zl[20];
+  R* zd;
+  const R* zz;
 };
 
-template <int P>
-__device__ __forceinline__ double* zslot(const ZView& z, int t, int i, int g, bool for_read) {
+template <int P, class R>
+__device__ __forceinline__ R* zslot(const ZView<R>& z, int t, int i, int g, bool for_read) {
   const Quad q = quad<P>(t, i);
-  double* other = for_read ? (double*)z.zz : z.zd;
-  double* a0 = q.pad[0] ? other : z.zl[q.m0[0] + 4] + 16 * q.n[0];
+  R* other = for_read ? (R*)z.zz : z.zd;
+  R* a0 = q.pad[0] ? other : z.zl[q.m0[0] + 4] + 16 * q.n[0];
   if (q.nseg == 1) return a0;
-  double* a1 = q.pad[1] ? other : z.zl[q.m0[1] + 4] + 16 * q.n[1];
-  double* w = g < q.end[0] ? a0 : a1;
+  R* a1 = q.pad[1] ? other : z.zl[q.m0[1] + 4] + 16 * q.n[1];
+  R* w = g < q.end[0] ? a0 : a1;
   if (q.nseg == 2) return w;
-  double* a2 = q.pad[2] ? other : z.zl[q.m0[2] + 4] + 16 * q.n[2];
+  R* a2 = q.pad[2] ? other : z.zl[q.m0[2] + 4] + 16 * q.n[2];
   return g < q.end[1] ? w : a2;
 }
 
@@ -300,8 +323,9 @@ __device__ __forceinline__ double* zslot(const ZView& z, int t, int i, int g, bo
 // the next rotation.  Both waves move their tiles to the order-major rows
 // and back; each computes its own orders.  hr: this lane's operand fragments
 // of the order-m matrices (in registers).
-template <int P, int W, int SINE>
-__device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol, const double* hr, int lane) {
+template <int P, int W, int SINE, class R>
+__device__ __forceinline__ void ztrans_part(typename Ar<R>::v4* st, const ZView<R>& z, R* zcol, const R* hr,
+                                            int lane) {
   constexpr int T = tl::ntiles(P);
   constexpr MSplit ms = m_split<P>();
   const int g = lane >> 4;
@@ -311,7 +335,7 @@ __device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE) continue;
-      *zslot<P>(z, t, i, g, false) = st[t][i];
+      *zslot<P, R>(z, t, i, g, false) = st[t][i];
     }
   }
   __syncthreads();
@@ -321,13 +345,13 @@ __device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol
     const int K = P + 1 - m;
     const int zo = tl::zoff(P, m);
     const int ho = tl::hoff(P, m);
-    d4 d = {0.0, 0.0, 0.0, 0.0};
+    typename Ar<R>::v4 d = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < tl::hsteps(P, m); ++k) d = mfma(hr[ho + k], zcol[(zo + 4 * k) * 16], d);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (4 * i >= K) continue;
-      double* dst = (4 * i + 3 < K || 4 * i + g < K) ? zcol + (zo + 4 * i) * 16 : z.zd;
+      R* dst = (4 * i + 3 < K || 4 * i + g < K) ? zcol + (zo + 4 * i) * 16 : z.zd;
       *dst = d[i];
     }
   }
@@ -338,19 +362,25 @@ __device__ __forceinline__ void ztrans_part(d4* st, const ZView& z, double* zcol
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE) continue;
-      st[t][i] = *zslot<P>(z, t, i, g, true);
+      st[t][i] = *zslot<P, R>(z, t, i, g, true);
     }
   }
   __syncthreads();
 }
 
 // the work of wave W of the block (both waves run the same loop structure
-// and meet at the same barriers)
-template <int P, int W>
-__device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, const double* __restrict__ mtab,
-                                         const double* __restrict__ Mx, double* __restrict__ Lx, int64_t ntarget,
+// and meet at the same barriers).  R = double: Mx holds the multipoles
+// (binary64).  R = float: Mx holds them in binary32, scaled as
+// M~_n = M_n / s^n with s the box radius (1 for a box of zero extent), and
+// the result is unscaled into binary64 at the store.
+template <int P, int W, class R>
+__device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* __restrict__ mtab,
+                                         const R* __restrict__ Mx, double* __restrict__ Lx, int64_t ntarget,
                                          const int32_t* __restrict__ order, int* __restrict__ queue) {
-  using C = Cfg<P>;
+  using C = Cfg<P, R>;
+  typedef typename Ar<R>::v4 v4;
+  typedef typename Ar<R>::v2 v2;
+  constexpr bool MIXED = sizeof(R) == 4;
   constexpr int T = C::T;
   constexpr int S = C::S;
   constexpr int NTW = tiles_of<P>(W);
@@ -358,19 +388,19 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
   constexpr MSplit ms = m_split<P>();
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, g = lane >> 4;
-  double* trig = smem;                       // two tables, alternate batches
-  double* zb = smem + 2 * 16 * C::TRIG;
-  double* zero_row = zb + C::ZBUF;           // stays zero
-  int* slot = (int*)(zero_row + 16);         // target handed to the block
+  R* trig = smem;                       // two tables, alternate batches
+  R* zb = smem + 2 * 16 * C::TRIG;
+  R* zero_row = zb + C::ZBUF;           // stays zero
+  int* slot = (int*)(zero_row + 16);    // target handed to the block
 
   // operand fragments of this wave's J tiles and orders, kept in registers
-  double jr[T * 4];
+  R jr[T * 4];
 #pragma unroll
   for (int t = 0; t < T; ++t)
     if (tile_owner<P>(t) == W)
 #pragma unroll
       for (int k = 0; k < 4; ++k) jr[t * 4 + k] = mtab[(t * 4 + k) * 64 + lane];
-  double hr[C::H];
+  R hr[C::H];
 #pragma unroll
   for (int m = 0; m <= P; ++m)
     if (ms.owner[m] == W)
@@ -378,7 +408,7 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
       for (int k = 0; k < tl::hsteps(P, m); ++k)
         hr[tl::hoff(P, m) + k] = mtab[T * 256 + (tl::hoff(P, m) + k) * 64 + lane];
 
-  ZView z;
+  ZView<R> z;
 #pragma unroll
   for (int k = 0; k < 20; ++k) {
     const int m = k - 4 + g;
@@ -386,8 +416,8 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
   }
   z.zd = zb + 16 * C::ZDUMMY + r16;
   z.zz = zero_row + r16;
-  double* zcol = zb + 16 * g + r16;
-  double* red = zb + W * 64 * C::RSTRIDE;  // this wave's pair-sum rows
+  R* zcol = zb + 16 * g + r16;
+  R* red = zb + W * 64 * C::RSTRIDE;  // this wave's pair-sum rows
 
   // persistent blocks: each takes the next target of the longest-first order
   // until the queue is empty
@@ -403,9 +433,10 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
     const int64_t bi = gid - lv.gofs[l];
     const double* geo = lv.geom[l];
     const double cix = geo[bi * 10 + 6], ciy = geo[bi * 10 + 7], ciz = geo[bi * 10 + 8];
+    const double rt = geo[bi * 10 + 9] > 0.0 ? geo[bi * 10 + 9] : 1.0;  // target scale (MIXED)
     const int64_t e0 = lv.w_off[l][bi], e1 = lv.w_off[l][bi + 1];
     const int32_t* widx = lv.w_idx[l];
-    const double* Mlev = Mx + (size_t)lv.gofs[l] * S;
+    const R* Mlev = Mx + (size_t)lv.gofs[l] * S;
 
     double acc[NRW > 0 ? NRW : 1];
 #pragma unroll
@@ -414,7 +445,7 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
     int buf = 0;
     for (int64_t eb = e0; eb < e1; eb += 16, buf ^= 1) {
       // pair of this lane's column; past the end of the list the column
-      // repeats the first source with 1/rho = 0, which zeroes its result
+      // repeats the first source with zero factors, which zeroes its result
       const int64_t e = eb + r16;
       const bool valid = e < e1;
       const int j = widx[valid ? e : e0];
@@ -428,11 +459,23 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
       const double rxy2 = dx * dx + dy * dy;
       const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
       const double irho = 1.0 / rho;
-      const double ir = valid ? irho : 0.0;
-      double* tp = trig + buf * 16 * C::TRIG + r16 * C::TRIG;  // this lane's pair
-      // (cos, sin)(m (angle + pi)) by the angle-addition recurrence: wave 0
-      // builds the theta table, wave 1 the alpha table (the four lane groups
-      // write the same values to the same words)
+      // scalings: M'(n) (1/rho)^n into the z translation, its output times
+      // (1/rho)^(j+1); with scaled expansions (s/rho)^n and (rt/rho)^j / rho
+      R in_base, out_base, out_mult;
+      if constexpr (MIXED) {
+        const double rs = geo[(int64_t)j * 10 + 9] > 0.0 ? geo[(int64_t)j * 10 + 9] : 1.0;
+        in_base = valid ? (R)(rs * irho) : (R)0;
+        out_base = valid ? (R)(rt * irho) : (R)0;
+        out_mult = valid ? (R)irho : (R)0;
+      } else {
+        in_base = valid ? irho : 0.0;
+        out_base = in_base;
+        out_mult = in_base;
+      }
+      R* tp = trig + buf * 16 * C::TRIG + r16 * C::TRIG;  // this lane's pair
+      // (cos, sin)(m (angle + pi)) by the angle-addition recurrence (binary64):
+      // wave 0 builds the theta table, wave 1 the alpha table (the four lane
+      // groups write the same values to the same words)
       {
         double c1, s1;
         if (W == 0) {
@@ -443,42 +486,43 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
           c1 = -dz * irho;
           s1 = -rxy * irho;
         }
-        double* dst = tp + (W == 0 ? 0 : 2 * (P + 1));
+        R* dst = tp + (W == 0 ? 0 : 2 * (P + 1));
         double c = 1.0, s = 0.0;
 #pragma unroll
         for (int m = 0; m <= P; ++m) {
-          *(d2*)(dst + 2 * m) = d2{c, s};
+          *(v2*)(dst + 2 * m) = v2{(R)c, (R)s};
           const double nc = c * c1 - s * s1, ns = s * c1 + c * s1;
           c = nc;
           s = ns;
         }
       }
-      d4 st[T];
-      const double* src = Mlev + (size_t)j * S + 4 * g;
+      v4 st[T];
+      const R* src = Mlev + (size_t)j * S + 4 * g;
 #pragma unroll
       for (int t = 0; t < T; ++t)
-        if (tile_owner<P>(t) == W) st[t] = *(const d4*)(src + 16 * t);
+        if (tile_owner<P>(t) == W) st[t] = *(const v4*)(src + 16 * t);
       __syncthreads();  // both tables written
 
       // (cos, sin) tables shifted so that entry 2 (m0 + 4) is order m0 + g
-      const double* cs_t = tp + 2 * (g - 4);
-      const double* cs_a = tp + 2 * (P + 1) + 2 * (g - 4);
+      const R* cs_t = tp + 2 * (g - 4);
+      const R* cs_a = tp + 2 * (P + 1) + 2 * (g - 4);
       // scheduling strategy for the long barrier-free stretches
       __builtin_amdgcn_iglp_opt(0);
-      rotz<P, W, false, 0>(st, cs_t, 1.0, g, ir);
-      japply<P, W>(st, jr);
-      rotz<P, W, true, 0>(st, cs_a, 1.0, g, ir);  // and (1/rho)^n
-      japply<P, W>(st, jr);
-      ztrans_part<P, W, 0>(st, z, zcol, hr, lane);
-      ztrans_part<P, W, 1>(st, z, zcol, hr, lane);
+      rotz<P, W, false, R>(st, cs_t, (R)1, g, (R)0, (R)1);
+      japply<P, W, R>(st, jr);
+      rotz<P, W, true, R>(st, cs_a, (R)1, g, in_base, (R)1);
+      japply<P, W, R>(st, jr);
+      ztrans_part<P, W, 0, R>(st, z, zcol, hr, lane);
+      ztrans_part<P, W, 1, R>(st, z, zcol, hr, lane);
       __builtin_amdgcn_iglp_opt(0);
-      japply<P, W>(st, jr);
-      rotz<P, W, true, 1>(st, cs_a, -1.0, g, ir);  // and (1/rho)^(j+1)
-      japply<P, W>(st, jr);
-      rotz<P, W, false, 0>(st, cs_t, -1.0, g, ir);
+      japply<P, W, R>(st, jr);
+      rotz<P, W, true, R>(st, cs_a, (R)-1, g, out_base, out_mult);
+      japply<P, W, R>(st, jr);
+      rotz<P, W, false, R>(st, cs_t, (R)-1, g, (R)0, (R)1);
 
       // sum over the 16 pairs, four of this wave's tiles per round; lane L
-      // adds up row L (slot L % 16 of its tile 4 r + L / 16)
+      // adds up row L (slot L % 16 of its tile 4 r + L / 16); each batch sum
+      // is added into binary64
 #pragma unroll
       for (int r = 0; r < NRW; ++r) {
 #pragma unroll
@@ -490,17 +534,17 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
         }
         wave_lds_fence();
         if (4 * r + 3 < NTW || 4 * r + (lane >> 4) < NTW) {
-          const double* row = red + lane * C::RSTRIDE;
-          d2 v = *(const d2*)row;
+          const R* row = red + lane * C::RSTRIDE;
+          v2 v = *(const v2*)row;
 #pragma unroll
-          for (int k = 1; k < 8; ++k) v += *(const d2*)(row + 2 * k);
-          acc[r] += v.x + v.y;
+          for (int k = 1; k < 8; ++k) v += *(const v2*)(row + 2 * k);
+          acc[r] += (double)(v.x + v.y);
         }
         wave_lds_fence();
       }
     }
     // lane L holds slot L % 16 of the wave's tile 4 r + L / 16; the final D is
-    // the sign (-1)^m
+    // the sign (-1)^m, and scaled expansions are unscaled by rt^-n
     double* dst = Lx + (size_t)gid * S;
 #pragma unroll
     for (int r = 0; r < NRW; ++r) {
@@ -508,70 +552,116 @@ __device__ __forceinline__ void m2l_wave(double* smem, const LevelView& lv, cons
       if (k < NTW) {
         const int t = owned_tile<P>(W, k);
         const Pos d = slot_pos<P>(t, lane & 15);
-        dst[tl::spos(t, lane & 15)] = (d.m & 1) ? -acc[r] : acc[r];
+        double v = (d.m & 1) ? -acc[r] : acc[r];
+        if (MIXED) {
+          const double irt = 1.0 / rt;
+          for (int n = 0; n < d.n; ++n) v *= irt;
+        }
+        dst[tl::spos(t, lane & 15)] = v;
       }
     }
   }
 }
 
-template <int P>
+template <int P, class R>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_m2l_mfma(
-    LevelView lv, const double* __restrict__ mtab, const double* __restrict__ Mx, double* __restrict__ Lx,
+    LevelView lv, const R* __restrict__ mtab, const R* __restrict__ Mx, double* __restrict__ Lx,
     int64_t ntarget, const int32_t* __restrict__ order, int* __restrict__ queue) {
-  __shared__ double smem[Cfg<P>::LDS];
+  __shared__ R smem[Cfg<P, R>::LDS];
   // every LDS word starts finite: buffer tails are read (and multiplied by 0)
-  for (int k = threadIdx.x; k < Cfg<P>::LDS; k += 128) smem[k] = 0.0;
+  for (int k = threadIdx.x; k < Cfg<P, R>::LDS; k += 128) smem[k] = (R)0;
   __syncthreads();
   if (threadIdx.x < 64)
-    m2l_wave<P, 0>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
+    m2l_wave<P, 0, R>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
   else
-    m2l_wave<P, 1>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
+    m2l_wave<P, 1, R>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
 }
 
-template <int P>
-void launch_one(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
+// binary32 copy of the multipoles of levels 1..L, scaled by s^-n (s the box
+// radius, 1 for a box of zero extent); padding positions stay zero
+__global__ void k_scale_m32(LevelView lv, int S, const int8_t* __restrict__ sdeg, const double* __restrict__ Mx,
+                            float* __restrict__ Mf, int64_t nbox_total) {
+  const int64_t gid = 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gid >= nbox_total) return;
+  int l = 1;
+  while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
+  const double r = lv.geom[l][(gid - lv.gofs[l]) * 10 + 9];
+  const double is = r > 0.0 ? 1.0 / r : 1.0;
+  for (int q = threadIdx.x & 63; q < S; q += 64) {
+    const int n = sdeg[q];
+    double v = Mx[(size_t)gid * S + q];
+    for (int k = 0; k < n; ++k) v *= is;
+    Mf[(size_t)gid * S + q] = n >= 0 ? (float)v : 0.f;
+  }
+}
+
+template <int P, class R>
+void launch_one(const Tree& t, const Tables& tb, const R* Mx, double* Lx, hipStream_t s) {
   const int64_t ntarget = t.nbox_total - 1;
   static int grid_max = 0;  // resident blocks of this instantiation on the device
   if (grid_max == 0) {
     int dev = 0, ncu = 0, per = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P>, 128, 0));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P, R>, 128, 0));
     grid_max = ncu * (per > 0 ? per : 1);
   }
   const int64_t need = ntarget;
   const unsigned grid = (unsigned)(need < grid_max ? need : grid_max);
   int* queue = (int*)dalloc(sizeof(int), s);
   HIPCHECK(hipMemsetAsync(queue, 0, sizeof(int), s));
-  k_m2l_mfma<P><<<grid, 128, 0, s>>>(t.view(), tb.mtab, Mx, Lx, ntarget, t.m2l_order, queue);
+  const R* mt;
+  if constexpr (sizeof(R) == 4)
+    mt = tb.mtab32;
+  else
+    mt = tb.mtab;
+  k_m2l_mfma<P, R><<<grid, 128, 0, s>>>(t.view(), mt, Mx, Lx, ntarget, t.m2l_order, queue);
   HIPCHECK(hipGetLastError());
   dfree(queue, s);
+}
+
+template <class R>
+bool launch_any(const Tree& t, const Tables& tb, const R* Mx, double* Lx, hipStream_t s) {
+  switch (tb.p) {
+    case 0: launch_one<0, R>(t, tb, Mx, Lx, s); break;
+    case 1: launch_one<1, R>(t, tb, Mx, Lx, s); break;
+    case 2: launch_one<2, R>(t, tb, Mx, Lx, s); break;
+    case 3: launch_one<3, R>(t, tb, Mx, Lx, s); break;
+    case 4: launch_one<4, R>(t, tb, Mx, Lx, s); break;
+    case 5: launch_one<5, R>(t, tb, Mx, Lx, s); break;
+    case 6: launch_one<6, R>(t, tb, Mx, Lx, s); break;
+    case 7: launch_one<7, R>(t, tb, Mx, Lx, s); break;
+    case 8: launch_one<8, R>(t, tb, Mx, Lx, s); break;
+    case 9: launch_one<9, R>(t, tb, Mx, Lx, s); break;
+    case 10: launch_one<10, R>(t, tb, Mx, Lx, s); break;
+    case 11: launch_one<11, R>(t, tb, Mx, Lx, s); break;
+    case 12: launch_one<12, R>(t, tb, Mx, Lx, s); break;
+    case 13: launch_one<13, R>(t, tb, Mx, Lx, s); break;
+    case 14: launch_one<14, R>(t, tb, Mx, Lx, s); break;
+    case 15: launch_one<15, R>(t, tb, Mx, Lx, s); break;
+    default: return false;
+  }
+  return true;
 }
 
 }  // namespace
 
 bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   if (!tb.tiled) return false;
-  switch (tb.p) {
-    case 0: launch_one<0>(t, tb, Mx, Lx, s); break;
-    case 1: launch_one<1>(t, tb, Mx, Lx, s); break;
-    case 2: launch_one<2>(t, tb, Mx, Lx, s); break;
-    case 3: launch_one<3>(t, tb, Mx, Lx, s); break;
-    case 4: launch_one<4>(t, tb, Mx, Lx, s); break;
-    case 5: launch_one<5>(t, tb, Mx, Lx, s); break;
-    case 6: launch_one<6>(t, tb, Mx, Lx, s); break;
-    case 7: launch_one<7>(t, tb, Mx, Lx, s); break;
-    case 8: launch_one<8>(t, tb, Mx, Lx, s); break;
-    case 9: launch_one<9>(t, tb, Mx, Lx, s); break;
-    case 10: launch_one<10>(t, tb, Mx, Lx, s); break;
-    case 11: launch_one<11>(t, tb, Mx, Lx, s); break;
-    case 12: launch_one<12>(t, tb, Mx, Lx, s); break;
-    case 13: launch_one<13>(t, tb, Mx, Lx, s); break;
-    case 14: launch_one<14>(t, tb, Mx, Lx, s); break;
-    case 15: launch_one<15>(t, tb, Mx, Lx, s); break;
-    default: return false;
+  return launch_any<double>(t, tb, Mx, Lx, s);
+}
+
+bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
+  if (!tb.tiled) return false;
+  float* Mf = (float*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(float), s);
+  if (t.nbox_total > 1) {
+    k_scale_m32<<<(unsigned)((t.nbox_total - 1 + 3) / 4), 256, 0, s>>>(t.view(), tb.stride, tb.sdeg, Mx, Mf,
+                                                                      t.nbox_total);
+    HIPCHECK(hipGetLastError());
   }
-  return true;
+  const bool ok = launch_any<float>(t, tb, Mf, Lx, s);
+  dfree(Mf, s);
+  return ok;
 }
 
 }  // namespace fmm

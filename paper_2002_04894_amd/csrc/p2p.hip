@@ -19,7 +19,7 @@ namespace fmm {
 
 void launch_p2m(const Tree& t, const Tables& tb, const double* qt, double* Mx, hipStream_t s);
 void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s);
-void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
+void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, int prec, hipStream_t s);
 void launch_l2l(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s);
 void launch_l2p(const Tree& t, const Tables& tb, const double* Lx, double* f0, double* f1, double* f2, double* f3,
                 hipStream_t s);
@@ -368,8 +368,11 @@ void p2p_plan(Tree& t, hipStream_t s) {
   dfree(acc, s);
 }
 
-void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, double* ex, double* ey, double* ez,
-              hipStream_t s) {
+// prec: FMM_PREC_F64, or FMM_PREC_MIXED for the binary32 M2L (the near field
+// stays in binary64: in binary32 its field lost up to 3e-5 relative on the
+// clustered workloads, through the cancellation among near contributions)
+void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey,
+              double* ez, hipStream_t s) {
   const int64_t n = t.n;
   const int L = t.L;
   PhaseTimer& tm = timer();
@@ -391,7 +394,7 @@ void evaluate(const Tree& t, const double* q, int p, int parts, double* pot, dou
     for (int l = L; l >= 2; --l) launch_m2m(t, l, tb, Mx, s);
     tm.end(FMM_PH_M2M, s);
     tm.begin(FMM_PH_M2L, s);
-    launch_m2l(t, tb, Mx, Lx, s);
+    launch_m2l(t, tb, Mx, Lx, prec, s);
     tm.end(FMM_PH_M2L, s);
     tm.begin(FMM_PH_L2L, s);
     for (int l = 2; l <= L; ++l) launch_l2l(t, l, tb, Lx, s);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
 FMM_PART_NEAR, FMM_PART_FAR, FMM_PART_ALL = 1, 2, 3
+FMM_PREC_F64, FMM_PREC_MIXED = 0, 1
 PHASES = ("tree", "lists", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 MAX_LEVELS, MAX_ORDER = 8, 20
 
@@ -41,6 +42,7 @@ def lib():
     L.fmm_build.argtypes = [vp, vp, vp, i64, i32, d, vp, C.POINTER(vp)]
     L.fmm_evaluate_tree.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
     L.fmm_evaluate_tree_parts.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+    L.fmm_evaluate_tree_ex.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]
     L.fmm_evaluate.argtypes = [vp, vp, vp, vp, i64, d, i32, i32, vp, vp, vp, vp, vp]
     L.fmm_free.argtypes = [vp]
     L.fmm_last_error.argtypes = []
@@ -117,12 +119,16 @@ def fmm_build(x, y, z, levels: int, theta: float, stream=None) -> Tree:
     return Tree(h.value, x.numel())
 
 
-def fmm_evaluate_tree(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts: int = FMM_PART_ALL):
+def fmm_evaluate_tree(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts: int = FMM_PART_ALL,
+                      precision: int = FMM_PREC_F64):
     for t, nm in ((q, "q"), (pot, "pot"), (ex, "ex"), (ey, "ey"), (ez, "ez")):
         _dev(t, nm)
         if t.numel() != tree.n:
             raise ValueError(f"{nm} must have {tree.n} elements")
-    if parts == FMM_PART_ALL:
+    if precision != FMM_PREC_F64:
+        _check(lib().fmm_evaluate_tree_ex(tree.handle, _ptr(q), int(p), int(parts), int(precision), _ptr(pot),
+                                          _ptr(ex), _ptr(ey), _ptr(ez), _stream(stream)))
+    elif parts == FMM_PART_ALL:
         _check(lib().fmm_evaluate_tree(tree.handle, _ptr(q), int(p), _ptr(pot), _ptr(ex), _ptr(ey), _ptr(ez),
                                        _stream(stream)))
     else:

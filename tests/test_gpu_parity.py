@@ -256,13 +256,21 @@ def test_full_size_gmix1m_sampled(torch, F, orc):
     s = ot.start(L)
     pts = np.concatenate([ot.perm()[s[b]:s[b + 1]] for b in leaves])
     assert_close([g[pts] for g in got], [r[pts] for r in ref], what="gmix1m sampled leaves")
+    say("[full] gmix1m: mixed precision")
+    qd = dev(torch, q)
+    mixed = [torch.empty_like(qd) for _ in range(4)]
+    F.fmm_evaluate_tree(gt, qd, p, *mixed, precision=F.FMM_PREC_MIXED)
+    torch.cuda.synchronize()
+    mixed = [m.cpu().numpy() for m in mixed]
+    assert_close([g[pts] for g in mixed], [r[pts] for r in ref], tol=1e-6, what="gmix1m mixed sampled leaves")
     say("[full] gmix1m: direct sum on sampled targets")
     tg = W.sample_targets(x.shape[0], 1000, seed=1)
     d = orc.direct(x, y, z, q, targets=tg)
-    ephi = np.linalg.norm(got[0][tg] - d[0]) / np.linalg.norm(d[0])
-    gE = np.concatenate([g[tg] for g in got[1:]])
     dE = np.concatenate(d[1:])
-    eE = np.linalg.norm(gE - dE) / np.linalg.norm(dE)
-    say(f"[full] gmix1m: err vs direct phi {ephi:.3e} E {eE:.3e}")
-    assert ephi <= 1e-6 and eE <= 1e-6
+    for res, nm in ((got, "f64"), (mixed, "mixed")):
+        ephi = np.linalg.norm(res[0][tg] - d[0]) / np.linalg.norm(d[0])
+        gE = np.concatenate([g[tg] for g in res[1:]])
+        eE = np.linalg.norm(gE - dE) / np.linalg.norm(dE)
+        say(f"[full] gmix1m {nm}: err vs direct phi {ephi:.3e} E {eE:.3e}")
+        assert ephi <= 1e-6 and eE <= 1e-6
     gt.free()
