@@ -21,7 +21,13 @@
  *    output is defined, nothing leaks, and fmm_last_error() returns a message
  *    (per calling thread).  Argument checks happen before any work is
  *    enqueued.  No exception crosses the ABI.
- *  - A tree handle may be used by one thread at a time.
+ *  - A tree handle may be used by one thread at a time.  Different handles
+ *    may be used by different threads at once, each on its own stream
+ *    (blocking or non-blocking).
+ *  - The first evaluation at an order p on a device makes that order's
+ *    operator tables (kept until the process ends) and waits for `stream`
+ *    once, so that the tables are on the device before any stream uses them;
+ *    every later evaluation is fully asynchronous.
  */
 #ifndef FMM_H
 #define FMM_H

@@ -291,18 +291,25 @@ HostTables make_host_tables(int p) {
 std::mutex g_tab_mu;
 std::map<std::pair<int, int>, Tables> g_tabs;  // (device, p) -> tables
 
+// copy enqueued on stream s; the caller waits for s before the tables are
+// used anywhere else
 template <class T>
-T* upload(const std::vector<T>& v) {
+T* upload(const std::vector<T>& v, hipStream_t s) {
   T* d = nullptr;
   const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
   if (hipMalloc((void**)&d, bytes) != hipSuccess) fail(FMM_ENOMEM, "hipMalloc failed for operator tables");
-  HIPCHECK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!v.empty()) HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return d;
 }
 
 }  // namespace
 
-const Tables& tables_for(int p, hipStream_t) {
+// The tables of order p on the current device, made on first use.  Later
+// calls use them from any stream, also non-blocking ones that do not order
+// after the null stream, and a synchronous copy from pageable memory may
+// return before its data has reached the device: so the uploads go on the
+// caller's stream and are waited for before the tables are published.
+const Tables& tables_for(int p, hipStream_t s) {
   int dev = 0;
   HIPCHECK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> g(g_tab_mu);
@@ -311,20 +318,21 @@ const Tables& tables_for(int p, hipStream_t) {
   HostTables h = make_host_tables(p);
   Tables t;
   t.p = p;
-  t.J = upload(h.J);
-  t.joff = upload(h.joff);
-  t.A = upload(h.A);
-  t.B = upload(h.B);
-  t.rc = upload(h.rc);
+  t.J = upload(h.J, s);
+  t.joff = upload(h.joff, s);
+  t.A = upload(h.A, s);
+  t.B = upload(h.B, s);
+  t.rc = upload(h.rc, s);
   t.stride = h.stride;
-  t.pos = upload(h.pos);
-  t.ipos = upload(h.ipos);
+  t.pos = upload(h.pos, s);
+  t.ipos = upload(h.ipos, s);
   t.tiled = h.tiled;
   if (h.tiled) {
-    t.mtab = upload(h.mtab);
-    t.mtab32 = upload(h.mtab32);
-    t.sdeg = upload(h.sdeg);
+    t.mtab = upload(h.mtab, s);
+    t.mtab32 = upload(h.mtab32, s);
+    t.sdeg = upload(h.sdeg, s);
   }
+  HIPCHECK(hipStreamSynchronize(s));  // also keeps h alive until the copies are done
   return g_tabs.emplace(std::make_pair(dev, p), t).first->second;
 }
 

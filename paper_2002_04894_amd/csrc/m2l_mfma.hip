@@ -598,14 +598,15 @@ __global__ void k_scale_m32(LevelView lv, int S, const int8_t* __restrict__ sdeg
 template <int P, class R>
 void launch_one(const Tree& t, const Tables& tb, const R* Mx, double* Lx, hipStream_t s) {
   const int64_t ntarget = t.nbox_total - 1;
-  static int grid_max = 0;  // resident blocks of this instantiation on the device
-  if (grid_max == 0) {
+  // resident blocks of this instantiation on the device (initialised once,
+  // thread-safe)
+  static const int grid_max = [] {
     int dev = 0, ncu = 0, per = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P, R>, 128, 0));
-    grid_max = ncu * (per > 0 ? per : 1);
-  }
+    return ncu * (per > 0 ? per : 1);
+  }();
   const int64_t need = ntarget;
   const unsigned grid = (unsigned)(need < grid_max ? need : grid_max);
   int* queue = (int*)dalloc(sizeof(int), s);
