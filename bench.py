@@ -34,11 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # 524308 KiB and WRITE_SIZE 1048576 KiB for 1048576 KiB moved each way.
 # Valid only for the kernel source it was taken on (hash below).
 M2L_COUNTERS = {
-    "sources_sha256": "3f15f5b0b5b205291b174b96bfc449a0c322a8ef7ca32d3a1a3b3c01841dc782",
+    "sources_sha256": "5b63c488d0e5bf3415dca20155f37c0e7d08c0ad0b41db571aea9a84dde0f060",
     "workload": "gmix1m",
-    "fetch_kib": 136356624.9375,
-    "write_kib": 9581895.5,
-    "fetch_scale": 1048576.0 / 524308.375,
+    "fetch_kib": 141123022.125,
+    "write_kib": 1053351.1875,
+    "fetch_scale": 1048576.0 / 524308.4375,
     "write_scale": 1.0,
 }
 
