@@ -385,7 +385,10 @@ typedef struct {
   int64_t n;
   int L;
   double theta;
+  double eta;              /* split parameter, Section 2.1.2 */
   const double *x, *y, *z; /* caller's arrays, input order */
+  int64_t m;               /* separate evaluation targets (may be 0) */
+  const double *tx, *ty, *tz;
   int32_t* perm;           /* tree order -> original index */
   orc_level* lev;          /* levels 0..L */
 } orc_tree;
@@ -406,11 +409,39 @@ static double coord(const orc_tree* t, int axis, int32_t i) {
   return c[i] + 0.0; /* -0.0 -> +0.0 */
 }
 
-/* One median bisection of the points perm[s..e) inside cell (lo, hi):
- * chooses the axis, reorders perm[s..e) stably into low | high and returns
- * the size of the low side; writes the split plane coordinate and axis. */
+/* One bisection of the points perm[s..e) inside cell (lo, hi): chooses the
+ * axis, reorders perm[s..e) stably into low | high and returns the size of
+ * the low side; writes the split plane coordinate and axis.
+ * eta = 1: the median split below.  eta < 1 (Section 2.1.2): the plane is the
+ * weighted average (1 - eta) * (cell midpoint) + eta * (the eta = 1 plane),
+ * and the points whose coordinate lies below it form the low side. */
+static int64_t bisect_median(const orc_tree* t, int32_t* perm, int64_t s, int64_t e, const double lo[3],
+                             const double hi[3], int* axis_out, double* plane_out, kv_t* kv, int32_t* tmp);
+
 static int64_t bisect(const orc_tree* t, int32_t* perm, int64_t s, int64_t e, const double lo[3],
-                      const double hi[3], int* axis_out, double* plane_out, kv_t* kv, int32_t* tmp) {
+                      const double hi[3], int* axis_out, double* plane_out, kv_t* kv, int32_t* tmp,
+                      int32_t* scratch) {
+  if (t->eta == 1.0) return bisect_median(t, perm, s, e, lo, hi, axis_out, plane_out, kv, tmp);
+  /* the eta = 1 plane, found on a copy so that perm keeps its order */
+  memcpy(scratch, perm + s, (size_t)(e - s) * sizeof(int32_t));
+  double plane1;
+  bisect_median(t, scratch, 0, e - s, lo, hi, axis_out, &plane1, kv, tmp);
+  const int axis = *axis_out;
+  const double mid = 0.5 * (lo[axis] + hi[axis]);
+  const double plane = (1.0 - t->eta) * mid + t->eta * plane1;
+  int64_t nl = 0, nh = 0;
+  for (int64_t i = s; i < e; ++i) {
+    if (coord(t, axis, perm[i]) < plane) scratch[nl++] = perm[i];
+    else tmp[nh++] = perm[i];
+  }
+  memcpy(perm + s, scratch, (size_t)nl * sizeof(int32_t));
+  memcpy(perm + s + nl, tmp, (size_t)nh * sizeof(int32_t));
+  *plane_out = plane;
+  return nl;
+}
+
+static int64_t bisect_median(const orc_tree* t, int32_t* perm, int64_t s, int64_t e, const double lo[3],
+                             const double hi[3], int* axis_out, double* plane_out, kv_t* kv, int32_t* tmp) {
   int axis = 0;
   double ext = hi[0] - lo[0];
   for (int a = 1; a < 3; ++a)
@@ -454,12 +485,18 @@ static void build_tree(orc_tree* t) {
     t->lev[l].geom = (double*)calloc((size_t)nb * 10, sizeof(double));
     t->lev[l].start = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
   }
-  /* root: tight bounding box */
+  /* root: tight bounding box of the sources and of the separate targets */
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) {
     if (n > 0) { lo[a] = hi[a] = coord(t, a, 0); }
     for (int64_t i = 1; i < n; ++i) {
       const double c = coord(t, a, (int32_t)i);
+      if (c < lo[a]) lo[a] = c;
+      if (c > hi[a]) hi[a] = c;
+    }
+    const double* tc = a == 0 ? t->tx : a == 1 ? t->ty : t->tz;
+    for (int64_t i = 0; i < t->m; ++i) {
+      const double c = tc[i] + 0.0;
       if (c < lo[a]) lo[a] = c;
       if (c > hi[a]) hi[a] = c;
     }
@@ -471,6 +508,7 @@ static void build_tree(orc_tree* t) {
 
   kv_t* kv = (kv_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(kv_t));
   int32_t* tmp = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t* scratch = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
   for (int l = 0; l < L; ++l) {
     orc_level* P = &t->lev[l];
     orc_level* C = &t->lev[l + 1];
@@ -488,7 +526,7 @@ static void build_tree(orc_tree* t) {
         for (int c = 0; c < cnt; ++c) {
           int axis;
           double plane;
-          const int64_t m = bisect(t, t->perm, cs[c], ce[c], clo[c], chi[c], &axis, &plane, kv, tmp);
+          const int64_t m = bisect(t, t->perm, cs[c], ce[c], clo[c], chi[c], &axis, &plane, kv, tmp, scratch);
           for (int h = 0; h < 2; ++h) {
             const int o = 2 * c + h;
             memcpy(nlo[o], clo[c], sizeof(nlo[o]));
@@ -517,6 +555,7 @@ static void build_tree(orc_tree* t) {
   }
   free(kv);
   free(tmp);
+  free(scratch);
   /* centres and radii, Section 2.1.1 */
   for (int l = 0; l <= L; ++l) {
     orc_level* V = &t->lev[l];
@@ -585,17 +624,29 @@ static void build_lists(orc_tree* t) {
 /* Public tree API                                                          */
 /* ------------------------------------------------------------------------ */
 
-void* orc_create(int64_t n, const double* x, const double* y, const double* z, int L, double theta) {
+/* Tree over n sources; the m separate targets (m may be 0) only widen the
+ * root cell so that every target lies in some leaf cell.  eta as in bisect. */
+void* orc_create_ex(int64_t n, const double* x, const double* y, const double* z, int64_t m, const double* tx,
+                    const double* ty, const double* tz, int L, double theta, double eta) {
   orc_tree* t = (orc_tree*)calloc(1, sizeof(orc_tree));
   t->n = n;
   t->L = L;
   t->theta = theta;
+  t->eta = eta;
   t->x = x;
   t->y = y;
   t->z = z;
+  t->m = m;
+  t->tx = tx;
+  t->ty = ty;
+  t->tz = tz;
   build_tree(t);
   build_lists(t);
   return t;
+}
+
+void* orc_create(int64_t n, const double* x, const double* y, const double* z, int L, double theta) {
+  return orc_create_ex(n, x, y, z, 0, NULL, NULL, NULL, L, theta, 1.0);
 }
 
 void orc_destroy(void* h) {
@@ -645,41 +696,32 @@ void orc_get_list(void* h, int l, int kind, int64_t* off, int32_t* idx) {
 /* Algorithm 4: L2P, P2P), for the points of the listed leaves.              */
 /* ------------------------------------------------------------------------ */
 
-/* parts: bit 0 = near field (P2P), bit 1 = far field (L2P).
- * leaves == NULL means every leaf.  Outputs are written at the original
- * point index of every point of the listed leaves; other entries untouched.
- * Returns 0 on success. */
-int orc_evaluate(void* h, const double* q, int p, int parts, int64_t nleaves, const int64_t* leaves, double* phi,
-                 double* ex, double* ey, double* ez) {
-  orc_tree* t = (orc_tree*)h;
-  if (p < 0 || p > ORC_PMAX) return -1;
+/* Upward and downward passes (Algorithm 1: P2M, M2M; Algorithm 3: M2L,
+ * L2L) on point data in tree order.  Local expansions are formed for the
+ * leaves flagged in need_leaf and their ancestors; returns them per level
+ * (Lx[l], l = 1..L; free with free_levels). */
+static void free_levels(cplx** X, int L) {
+  if (!X) return;
+  for (int l = 0; l <= L; ++l) free(X[l]);
+  free(X);
+}
+
+static cplx** far_pass(const orc_tree* t, const double* px, const double* py, const double* pz, const double* pq,
+                       int p, const char* need_leaf) {
   const int L = t->L;
   const int nt = NTERMS(p);
   const orc_level* leaf = &t->lev[L];
-  if (leaves == NULL) nleaves = leaf->nbox;
-
-  /* point data in tree order */
-  const int64_t n = t->n;
-  double* px = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* py = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* pz = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* pq = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  for (int64_t i = 0; i < n; ++i) {
-    const int32_t o = t->perm[i];
-    px[i] = t->x[o]; py[i] = t->y[o]; pz[i] = t->z[o]; pq[i] = q[o];
-  }
-
-  /* which boxes need a local expansion: ancestors of the listed leaves */
   char** need = (char**)calloc((size_t)L + 1, sizeof(char*));
   for (int l = 0; l <= L; ++l) need[l] = (char*)calloc((size_t)t->lev[l].nbox, 1);
-  for (int64_t s = 0; s < nleaves; ++s) {
-    int64_t b = leaves ? leaves[s] : s;
+  for (int64_t s = 0; s < leaf->nbox; ++s) {
+    if (!need_leaf[s]) continue;
+    int64_t b = s;
     for (int l = L; l >= 0; --l, b /= 8) need[l][b] = 1;
   }
 
   cplx** Mx = (cplx**)calloc((size_t)L + 1, sizeof(cplx*));
   cplx** Lx = (cplx**)calloc((size_t)L + 1, sizeof(cplx*));
-  if ((parts & 2) && L >= 1) {
+  {
     for (int l = 1; l <= L; ++l) {
       Mx[l] = (cplx*)calloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
       Lx[l] = (cplx*)calloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
@@ -729,6 +771,42 @@ int orc_evaluate(void* h, const double* q, int p, int parts, int64_t nleaves, co
     }
   }
 
+  for (int l = 0; l <= L; ++l) free(need[l]);
+  free(need);
+  free_levels(Mx, L);
+  return Lx;
+}
+
+/* parts: bit 0 = near field (P2P), bit 1 = far field (L2P).
+ * leaves == NULL means every leaf.  Outputs are written at the original
+ * point index of every point of the listed leaves; other entries untouched.
+ * Returns 0 on success. */
+int orc_evaluate(void* h, const double* q, int p, int parts, int64_t nleaves, const int64_t* leaves, double* phi,
+                 double* ex, double* ey, double* ez) {
+  orc_tree* t = (orc_tree*)h;
+  if (p < 0 || p > ORC_PMAX) return -1;
+  const int L = t->L;
+  const int nt = NTERMS(p);
+  const orc_level* leaf = &t->lev[L];
+  if (leaves == NULL) nleaves = leaf->nbox;
+
+  /* point data in tree order */
+  const int64_t n = t->n;
+  double* px = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* py = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pz = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pq = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t o = t->perm[i];
+    px[i] = t->x[o]; py[i] = t->y[o]; pz[i] = t->z[o]; pq[i] = q[o];
+  }
+
+  /* which boxes need a local expansion: ancestors of the listed leaves */
+  char* need_leaf = (char*)calloc((size_t)leaf->nbox, 1);
+  for (int64_t s = 0; s < nleaves; ++s) need_leaf[leaves ? leaves[s] : s] = 1;
+  cplx** Lx = ((parts & 2) && L >= 1) ? far_pass(t, px, py, pz, pq, p, need_leaf) : NULL;
+  free(need_leaf);
+
   for (int64_t s = 0; s < nleaves; ++s) {
     const int64_t b = leaves ? leaves[s] : s;
     const double* g = leaf->geom + b * 10;
@@ -762,8 +840,107 @@ int orc_evaluate(void* h, const double* q, int p, int parts, int64_t nleaves, co
     }
   }
 
-  for (int l = 0; l <= L; ++l) { free(need[l]); free(Mx[l]); free(Lx[l]); }
-  free(need); free(Mx); free(Lx);
+  free_levels(Lx, L);
+  free(px); free(py); free(pz); free(pq);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Evaluation at separate targets (the convergence test of Section 3.1      */
+/* evaluates at points that are not sources).                               */
+/* ------------------------------------------------------------------------ */
+
+/* The leaf whose cell holds target (x, y, z): from the root, at every level
+ * the first of the eight children (in child order) whose closed cell
+ * contains the point.  The children's cells tile the parent's cell, so one
+ * always does for a point inside the root cell; -1 outside it. */
+int64_t orc_locate(void* h, double x, double y, double z) {
+  const orc_tree* t = (const orc_tree*)h;
+  const double v[3] = {x + 0.0, y + 0.0, z + 0.0};
+  const double* g0 = t->lev[0].geom;
+  for (int a = 0; a < 3; ++a)
+    if (!(v[a] >= g0[a] && v[a] <= g0[3 + a])) return -1;
+  int64_t b = 0;
+  for (int l = 1; l <= t->L; ++l) {
+    const double* g = t->lev[l].geom;
+    int64_t found = -1;
+    for (int c = 0; c < 8 && found < 0; ++c) {
+      const int64_t j = 8 * b + c;
+      int in = 1;
+      for (int a = 0; a < 3; ++a)
+        if (!(v[a] >= g[j * 10 + a] && v[a] <= g[j * 10 + 3 + a])) in = 0;
+      if (in) found = j;
+    }
+    if (found < 0) return -1;
+    b = found;
+  }
+  return b;
+}
+
+/* phi and E = -grad phi at the tree's m separate targets (input order):
+ * far field from the local expansion of the target's leaf (L2P), near field
+ * from the sources of the leaves strongly connected to it (P2P; a source at
+ * the target's own position contributes nothing).  parts as in
+ * orc_evaluate.  Returns 0, or -1 for a bad order, -2 for a target outside
+ * the root cell. */
+int orc_evaluate_targets(void* h, const double* q, int p, int parts, double* phi, double* ex, double* ey,
+                         double* ez) {
+  orc_tree* t = (orc_tree*)h;
+  if (p < 0 || p > ORC_PMAX) return -1;
+  const int L = t->L;
+  const int nt = NTERMS(p);
+  const orc_level* leaf = &t->lev[L];
+  const int64_t n = t->n, m = t->m;
+  int64_t* tleaf = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+  for (int64_t k = 0; k < m; ++k) {
+    tleaf[k] = orc_locate(h, t->tx[k], t->ty[k], t->tz[k]);
+    if (tleaf[k] < 0) { free(tleaf); return -2; }
+  }
+  double* px = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* py = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pz = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pq = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t o = t->perm[i];
+    px[i] = t->x[o]; py[i] = t->y[o]; pz[i] = t->z[o]; pq[i] = q[o];
+  }
+  char* need_leaf = (char*)calloc((size_t)leaf->nbox, 1);
+  for (int64_t k = 0; k < m; ++k) need_leaf[tleaf[k]] = 1;
+  cplx** Lx = ((parts & 2) && L >= 1) ? far_pass(t, px, py, pz, pq, p, need_leaf) : NULL;
+  free(need_leaf);
+
+  for (int64_t k = 0; k < m; ++k) {
+    const int64_t b = tleaf[k];
+    const double x = t->tx[k] + 0.0, y = t->ty[k] + 0.0, z = t->tz[k] + 0.0;
+    double f = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    if (Lx) {
+      const double* g = leaf->geom + b * 10;
+      orc_l2p_add(p, Lx[L] + b * nt, g[6], g[7], g[8], x, y, z, &f, &fx, &fy, &fz);
+    }
+    if (parts & 1) {
+      for (int64_t e = leaf->s_off[b]; e < leaf->s_off[b + 1]; ++e) {
+        const int64_t j = leaf->s_idx[e];
+        for (int64_t si = leaf->start[j]; si < leaf->start[j + 1]; ++si) {
+          const double dx = x - px[si], dy = y - py[si], dz = z - pz[si];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) continue;
+          const double r = sqrt(r2);
+          const double inv = 1.0 / r;
+          const double inv3 = inv / r2;
+          f += pq[si] * inv;
+          fx += pq[si] * dx * inv3;
+          fy += pq[si] * dy * inv3;
+          fz += pq[si] * dz * inv3;
+        }
+      }
+    }
+    phi[k] = f;
+    ex[k] = fx;
+    ey[k] = fy;
+    ez[k] = fz;
+  }
+  free_levels(Lx, L);
+  free(tleaf);
   free(px); free(py); free(pz); free(pq);
   return 0;
 }

@@ -36,6 +36,12 @@ def _load():
     lib.orc_direct.restype = None
     lib.orc_create.argtypes = [i64, _dp, _dp, _dp, i32, d]
     lib.orc_create.restype = C.c_void_p
+    lib.orc_create_ex.argtypes = [i64, _dp, _dp, _dp, i64, C.c_void_p, C.c_void_p, C.c_void_p, i32, d, d]
+    lib.orc_create_ex.restype = C.c_void_p
+    lib.orc_locate.argtypes = [C.c_void_p, d, d, d]
+    lib.orc_locate.restype = i64
+    lib.orc_evaluate_targets.argtypes = [C.c_void_p, _dp, i32, i32, _dp, _dp, _dp, _dp]
+    lib.orc_evaluate_targets.restype = i32
     lib.orc_destroy.argtypes = [C.c_void_p]
     lib.orc_get_perm.argtypes = [C.c_void_p, _i32p]
     lib.orc_get_geom.argtypes = [C.c_void_p, i32, _dp]
@@ -88,13 +94,25 @@ def direct(x, y, z, q, targets=None):
 class Tree:
     """ORB tree + theta-criterion lists + FMM evaluation (all on the CPU)."""
 
-    def __init__(self, x, y, z, levels: int, theta: float):
+    def __init__(self, x, y, z, levels: int, theta: float, eta: float = 1.0, targets=None):
+        """targets: optional (tx, ty, tz) of separate evaluation points; they
+        widen the root cell (see orc_create_ex).  eta: split parameter."""
         lib = _load()
         self._x, self._y, self._z = map(_f64, (x, y, z))
         self.n = self._x.shape[0]
         self.levels = int(levels)
         self.theta = float(theta)
-        self._h = lib.orc_create(self.n, self._x, self._y, self._z, self.levels, self.theta)
+        self.eta = float(eta)
+        if targets is None:
+            self._t = None
+            self.m = 0
+            ptrs = (None, None, None)
+        else:
+            self._t = tuple(map(_f64, targets))
+            self.m = self._t[0].shape[0]
+            ptrs = tuple(a.ctypes.data_as(C.c_void_p) for a in self._t)
+        self._h = lib.orc_create_ex(self.n, self._x, self._y, self._z, self.m, *ptrs, self.levels, self.theta,
+                                    self.eta)
 
     def close(self):
         if self._h:
@@ -146,6 +164,22 @@ class Tree:
         rc = lib.orc_evaluate(self._h, q, int(p), int(parts), nl, lp, *out)
         if rc != 0:
             raise ValueError(f"orc_evaluate failed ({rc})")
+        return tuple(out)
+
+
+    def locate(self, x, y, z) -> int:
+        """Leaf whose cell holds the point (first child in order at every
+        level), -1 outside the root cell."""
+        return int(_load().orc_locate(self._h, float(x), float(y), float(z)))
+
+    def evaluate_targets(self, q, p: int, parts: int = 3):
+        """phi, ex, ey, ez at the separate targets, in their input order."""
+        if self._t is None:
+            raise ValueError("this tree has no separate targets")
+        out = [np.empty(self.m) for _ in range(4)]
+        rc = _load().orc_evaluate_targets(self._h, _f64(q), int(p), int(parts), *out)
+        if rc != 0:
+            raise ValueError(f"orc_evaluate_targets failed ({rc})")
         return tuple(out)
 
 
