@@ -111,6 +111,49 @@ int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, d
 int fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
                          double* ey, double* ez, void* stream);
 
+/*
+ * fmm_build with the split parameter eta and separate evaluation targets
+ * (Section 2.1.2; the convergence test of Section 3.1 evaluates at points
+ * that are not sources).
+ *   x, y, z, n, levels, theta   as in fmm_build.
+ *   tx, ty, tz   device, m doubles each: target coordinates (finite,
+ *                |coord| <= 1e300); NULL allowed when m = 0.  Read during
+ *                the call only.
+ *   m            0 <= m <= FMM_MAX_POINTS.
+ *   eta          0 <= eta <= 1.  Every box is split by three successive
+ *                bisections along the longest edge of the current cell, at
+ *                the plane (1 - eta) * (cell midpoint) + eta * (median plane),
+ *                where the median plane lies midway between the two middle
+ *                coordinates.  eta = 1 is fmm_build's median split (the low
+ *                side gets floor(n/2) points, ties by input order); for
+ *                eta < 1 the points strictly below the plane form the low
+ *                side, so children may hold unequal numbers of points or none.
+ * The root cell is the bounding box of the sources and the targets.  Each
+ * target belongs to the leaf reached from the root by taking, at every
+ * level, the first child (in child order) whose closed cell holds it.
+ * Synchronises `stream` as fmm_build does, plus once for the targets.
+ */
+int fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, const double* tx, const double* ty,
+                 const double* tz, int64_t m, int levels, double theta, double eta, void* stream, fmm_tree** out);
+
+/*
+ * Potential and field at the tree's m separate targets, for charges q on
+ * its sources: the far field from the local expansion of the target's leaf
+ * (L2P), the near field from the sources of the leaves strongly connected to
+ * it (P2P); a source at the target's own position contributes nothing.
+ *   q                  device, n doubles, caller's source order.
+ *   p, parts, precision  as in fmm_evaluate_tree_ex.
+ *   pot, ex, ey, ez    device, m doubles each, written in the caller's
+ *                      target order (may be NULL when m = 0).
+ * Fully asynchronous on `stream`.  A tree without targets does nothing.
+ */
+int fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+                         double* ey, double* ez, void* stream);
+
+/* Number of separate targets of a tree and, when `leaf` (host, m int32) is
+ * not NULL, the leaf that holds each of them (caller's target order). */
+int fmm_tree_targets(const fmm_tree* tree, int64_t* m, int32_t* leaf);
+
 /* One-shot form: fmm_build + fmm_evaluate_tree + fmm_free.  All arrays are
  * device arrays of n doubles. */
 int fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,

@@ -69,6 +69,16 @@ void release(Tree& t) {
   t.p2p_seg_e0 = nullptr;
   t.p2p_leaf_seg = nullptr;
   t.p2p_leaf_part = nullptr;
+  f(t.tx);
+  f(t.ty);
+  f(t.tz);
+  f(t.tperm);
+  f(t.tleaf);
+  f(t.tstart);
+  f(t.p2p_leaf_tpart);
+  t.tx = t.ty = t.tz = nullptr;
+  t.tperm = t.tleaf = t.tstart = nullptr;
+  t.p2p_leaf_tpart = nullptr;
   for (Level& V : t.lev) {
     f(V.geom);
     f(V.start);
@@ -192,25 +202,35 @@ void ensure_device() {
   }
 }
 
-fmm_tree* build_impl(const double* x, const double* y, const double* z, int64_t n, int levels, double theta,
+fmm_tree* build_impl(const double* x, const double* y, const double* z, int64_t n, const double* tx,
+                     const double* ty, const double* tz, int64_t m, int levels, double theta, double eta,
                      hipStream_t s) {
   validate_points(x, y, z, n);
   validate_tree_args(levels, theta);
+  if (!(eta >= 0.0 && eta <= 1.0)) fail(FMM_EINVAL, "eta must be in [0, 1]");
+  if (m < 0 || m > FMM_MAX_POINTS) fail(FMM_EINVAL, "m must be in [0, 2^31-1]");
+  if (m > 0 && (!tx || !ty || !tz)) fail(FMM_EINVAL, "target pointer is NULL");
   ensure_device();
   fmm_tree* h = new fmm_tree();
   fmm::Tree& t = h->t;
   t.n = n;
   t.L = levels;
   t.theta = theta;
+  t.eta = eta;
+  t.m = m;
   t.stream = s;
   try {
     fmm::timer().reset();
     fmm::timer().begin(FMM_PH_TREE, s);
-    fmm::tree_build(t, x, y, z, s);
+    fmm::tree_build(t, x, y, z, tx, ty, tz, s);
     fmm::timer().end(FMM_PH_TREE, s);
     fmm::timer().begin(FMM_PH_LISTS, s);
     fmm::lists_build(t, s);
     fmm::p2p_plan(t, s);
+    if (m > 0) {
+      fmm::targets_build(t, s);
+      fmm::p2p_plan_targets(t, s);
+    }
     fmm::timer().end(FMM_PH_LISTS, s);
   } catch (...) {
     fmm::release(t);
@@ -234,7 +254,41 @@ int fmm_build(const double* x, const double* y, const double* z, int64_t n, int 
   return fmm::guarded([&] {
     if (!out) fail(FMM_EINVAL, "out is NULL");
     *out = nullptr;
-    *out = build_impl(x, y, z, n, levels, theta, (hipStream_t)stream);
+    *out = build_impl(x, y, z, n, nullptr, nullptr, nullptr, 0, levels, theta, 1.0, (hipStream_t)stream);
+  });
+}
+
+int fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, const double* tx, const double* ty,
+                 const double* tz, int64_t m, int levels, double theta, double eta, void* stream, fmm_tree** out) {
+  return fmm::guarded([&] {
+    if (!out) fail(FMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    *out = build_impl(x, y, z, n, tx, ty, tz, m, levels, theta, eta, (hipStream_t)stream);
+  });
+}
+
+int fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+                         double* ey, double* ez, void* stream) {
+  return fmm::guarded([&] {
+    fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
+    if (!q) fail(FMM_EINVAL, "charge pointer is NULL");
+    if (p < 0 || p > FMM_MAX_ORDER) fail(FMM_EINVAL, "p must be in [0, 20]");
+    if (t.m > 0 && (!pot || !ex || !ey || !ez)) fail(FMM_EINVAL, "output pointer is NULL");
+    if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
+    t.stream = (hipStream_t)stream;
+    fmm::evaluate_targets(t, q, p, parts, precision, pot, ex, ey, ez, (hipStream_t)stream);
+  });
+}
+
+int fmm_tree_targets(const fmm_tree* tree, int64_t* m, int32_t* leaf) {
+  return fmm::guarded([&] {
+    const fmm::Tree& t = get(tree);
+    if (m) *m = t.m;
+    if (leaf && t.m > 0) {
+      HIPCHECK(hipStreamSynchronize(t.stream));
+      HIPCHECK(hipMemcpy(leaf, t.tleaf, t.m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
   });
 }
 
@@ -267,7 +321,7 @@ int fmm_evaluate(const double* x, const double* y, const double* z, const double
     validate_tree_args(levels, theta);
     validate_eval_args(q, p, pot, ex, ey, ez);
     hipStream_t s = (hipStream_t)stream;
-    fmm_tree* h = build_impl(x, y, z, n, levels, theta, s);
+    fmm_tree* h = build_impl(x, y, z, n, nullptr, nullptr, nullptr, 0, levels, theta, 1.0, s);
     try {
       fmm::evaluate(h->t, q, p, FMM_PART_ALL, FMM_PREC_F64, pot, ex, ey, ez, s);
     } catch (...) {

@@ -660,17 +660,19 @@ __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* _
 }
 
 // ---- L2P: far field at the points of each leaf (phi and E = -grad phi) ----
-__global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const double* __restrict__ px,
-                                            const double* __restrict__ py, const double* __restrict__ pz,
-                                            const double* __restrict__ Lx, double* __restrict__ fphi,
-                                            double* __restrict__ fex, double* __restrict__ fey,
-                                            double* __restrict__ fez) {
+// The evaluation points of leaf b are [start[b], start[b+1]) of (px, py, pz):
+// the leaf's own sources, or the separate targets grouped by leaf.
+__global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const int32_t* __restrict__ start,
+                                            const double* __restrict__ px, const double* __restrict__ py,
+                                            const double* __restrict__ pz, const double* __restrict__ Lx,
+                                            double* __restrict__ fphi, double* __restrict__ fex,
+                                            double* __restrict__ fey, double* __restrict__ fez) {
   const int lane = threadIdx.x;
   const int L = lv.L, p = tb.p, P1 = p + 1;
   const int64_t b = blockIdx.x;
   const double* g = lv.geom[L] + b * 10;
   const double cx = g[6], cy = g[7], cz = g[8];
-  const int s0 = lv.start[L][b], s1 = lv.start[L][b + 1];
+  const int s0 = start[b], s1 = start[b + 1];
   const double* Lc = Lx + (size_t)(lv.gofs[L] + b) * tb.stride;
   const int* pos = tb.pos;
   const double* am = tb.rc;
@@ -766,9 +768,9 @@ void launch_l2l(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t 
   k_l2l<<<(unsigned)t.lev[l].nbox, 64, 0, s>>>(t.view(), l, make_xt(tb), Lx);
   HIPCHECK(hipGetLastError());
 }
-void launch_l2p(const Tree& t, const Tables& tb, const double* Lx, double* f0, double* f1, double* f2, double* f3,
-                hipStream_t s) {
-  k_l2p<<<(unsigned)t.lev[t.L].nbox, 64, 0, s>>>(t.view(), make_xt(tb), t.px, t.py, t.pz, Lx, f0, f1, f2, f3);
+void launch_l2p(const Tree& t, const Tables& tb, const double* Lx, const int32_t* start, const double* px,
+                const double* py, const double* pz, double* f0, double* f1, double* f2, double* f3, hipStream_t s) {
+  k_l2p<<<(unsigned)t.lev[t.L].nbox, 64, 0, s>>>(t.view(), make_xt(tb), start, px, py, pz, Lx, f0, f1, f2, f3);
   HIPCHECK(hipGetLastError());
 }
 

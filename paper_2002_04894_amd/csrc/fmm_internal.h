@@ -61,6 +61,7 @@ struct Tree {
   int64_t n = 0;
   int L = 0;
   double theta = 0;
+  double eta = 1.0;  // split parameter (Section 2.1.2): 1 = median planes
   hipStream_t stream = nullptr;
   // points in tree order
   double* px = nullptr;
@@ -80,6 +81,17 @@ struct Tree {
   int64_t* p2p_leaf_seg = nullptr;   // [nleaf + 1] first segment of each leaf
   int64_t* p2p_leaf_part = nullptr;  // [nleaf + 1] first partial sum of each split leaf
   int64_t p2p_npart = 0;             // partial sums (target x segment) of split leaves
+  // separate evaluation targets (m may be 0), grouped by the leaf that holds
+  // them; before targets_build the coordinate arrays hold the caller's order
+  int64_t m = 0;
+  double* tx = nullptr;
+  double* ty = nullptr;
+  double* tz = nullptr;
+  int32_t* tperm = nullptr;           // [m] grouped order -> caller's index
+  int32_t* tleaf = nullptr;           // [m] leaf of each target, caller's order
+  int32_t* tstart = nullptr;          // [nleaf + 1] target range of each leaf
+  int64_t* p2p_leaf_tpart = nullptr;  // [nleaf + 1] first partial sum of each split leaf (targets)
+  int64_t p2p_ntpart = 0;
   LevelView view() const;
 };
 
@@ -116,9 +128,18 @@ struct PhaseTimer {
 PhaseTimer& timer();
 
 // ---- launch wrappers ----
-void tree_build(Tree& t, const double* x, const double* y, const double* z, hipStream_t s);
+// t.n, t.L, t.eta and, when t.m > 0, the targets (tx, ty, tz, caller's
+// order) are inputs; the targets only widen the root cell
+void tree_build(Tree& t, const double* x, const double* y, const double* z, const double* tx, const double* ty,
+                const double* tz, hipStream_t s);
+// locates the targets in the leaves and groups them by leaf (after lists)
+void targets_build(Tree& t, hipStream_t s);
 void lists_build(Tree& t, hipStream_t s);
 void p2p_plan(Tree& t, hipStream_t s);
+// partial-sum layout of the split leaves for the separate targets
+void p2p_plan_targets(Tree& t, hipStream_t s);
+void evaluate_targets(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey,
+                      double* ez, hipStream_t s);
 void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey, double* ez,
               hipStream_t s);
 

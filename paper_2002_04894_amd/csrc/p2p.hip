@@ -21,8 +21,8 @@ void launch_p2m(const Tree& t, const Tables& tb, const double* qt, double* Mx, h
 void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s);
 void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, int prec, hipStream_t s);
 void launch_l2l(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s);
-void launch_l2p(const Tree& t, const Tables& tb, const double* Lx, double* f0, double* f1, double* f2, double* f3,
-                hipStream_t s);
+void launch_l2p(const Tree& t, const Tables& tb, const double* Lx, const int32_t* start, const double* px,
+                const double* py, const double* pz, double* f0, double* f1, double* f2, double* f3, hipStream_t s);
 
 namespace {
 
@@ -127,12 +127,17 @@ __global__ void k_sum64(int64_t n, const int64_t* __restrict__ v, unsigned long 
 // LDS serves two interactions.  Sources are staged in chunks of up to kP2PBuf
 // points gathered from consecutive entries of the segment: the lanes take the
 // chunk's points in a flat order, so all their loads are in flight together.
+// The targets of leaf b are [tstart[b], tstart[b+1]) of (tx, ty, tz), written
+// to index tperm[.] of the outputs: the leaf's own sources (tstart = start,
+// tx = px, tperm = perm) or the separate targets grouped by leaf.
 __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restrict__ seg_leaf,
                                             const int64_t* __restrict__ seg_e0, const int64_t* __restrict__ leaf_seg,
                                             const int64_t* __restrict__ leaf_part, const int32_t* __restrict__ start,
                                             const int64_t* __restrict__ s_off, const int32_t* __restrict__ s_idx,
                                             const double* __restrict__ px, const double* __restrict__ py,
                                             const double* __restrict__ pz, const double* __restrict__ qt,
+                                            const int32_t* __restrict__ tstart, const double* __restrict__ tx,
+                                            const double* __restrict__ ty, const double* __restrict__ tz,
                                             const int32_t* __restrict__ perm, const double* __restrict__ f0,
                                             const double* __restrict__ f1, const double* __restrict__ f2,
                                             const double* __restrict__ f3, double4* __restrict__ part,
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restr
   const int64_t b = seg_leaf[g];
   const int64_t sb = leaf_seg[b], ns = leaf_seg[b + 1] - sb, r = g - sb;
   const int64_t e0 = seg_e0[g], e1 = r + 1 < ns ? seg_e0[g + 1] : s_off[b + 1];
-  const int t0 = start[b], t1 = start[b + 1];
+  const int t0 = tstart[b], t1 = tstart[b + 1];
   const int nt = t1 - t0;
   double4* pout = ns > 1 ? part + leaf_part[b] + r * nt : nullptr;  // partial sums, by target - t0
   // lanes = (target pair, source stream)
@@ -156,8 +161,8 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restr
     const int ta = c0 + tl, tb = c0 + tl + TT;
     const bool va = ta < t1, vb = tb < t1;
     const int ua = va ? ta : t0, ub = vb ? tb : t0;
-    const double xa = px[ua], ya = py[ua], za = pz[ua];
-    const double xb = px[ub], yb = py[ub], zb = pz[ub];
+    const double xa = tx[ua], ya = ty[ua], za = tz[ua];
+    const double xb = tx[ub], yb = ty[ub], zb = tz[ub];
     double fa = 0.0, gxa = 0.0, gya = 0.0, gza = 0.0;
     double fb = 0.0, gxb = 0.0, gyb = 0.0, gzb = 0.0;
     auto interact = [&](const double4 s) {
@@ -326,7 +331,32 @@ __global__ __launch_bounds__(256) void k_p2p_final(int64_t nleaf, const int32_t*
   }
 }
 
+// partial sums needed for the separate targets of leaf i
+__global__ void k_tpart_count(int64_t nleaf, const int32_t* __restrict__ tstart, const int64_t* __restrict__ leaf_seg,
+                              int64_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nleaf) return;
+  const int64_t ns = leaf_seg[i + 1] - leaf_seg[i];
+  cnt[i] = ns > 1 ? ns * (int64_t)(tstart[i + 1] - tstart[i]) : 0;
+}
+
 }  // namespace
+
+void p2p_plan_targets(Tree& t, hipStream_t s) {
+  const int64_t nleaf = t.lev[t.L].nbox;
+  int64_t* pcnt = (int64_t*)dalloc(nleaf * sizeof(int64_t), s);
+  k_tpart_count<<<(unsigned)((nleaf + 255) / 256), 256, 0, s>>>(nleaf, t.tstart, t.p2p_leaf_seg, pcnt);
+  HIPCHECK(hipGetLastError());
+  t.p2p_leaf_tpart = (int64_t*)dalloc((nleaf + 1) * sizeof(int64_t), s);
+  scan_counts(pcnt, t.p2p_leaf_tpart, nleaf, 0, s);
+  int64_t* h = nullptr;
+  HIPCHECK(hipHostMalloc((void**)&h, sizeof(int64_t), hipHostMallocDefault));
+  HIPCHECK(hipMemcpyAsync(h, t.p2p_leaf_tpart + nleaf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  t.p2p_ntpart = *h;
+  HIPCHECK(hipHostFree(h));
+  dfree(pcnt, s);
+}
 
 void p2p_plan(Tree& t, hipStream_t s) {
   const Level& V = t.lev[t.L];
@@ -371,61 +401,102 @@ void p2p_plan(Tree& t, hipStream_t s) {
 // prec: FMM_PREC_F64, or FMM_PREC_MIXED for the binary32 M2L (the near field
 // stays in binary64: in binary32 its field lost up to 3e-5 relative on the
 // clustered workloads, through the cancellation among near contributions)
-void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey,
-              double* ez, hipStream_t s) {
-  const int64_t n = t.n;
+namespace {
+
+// Upward and downward passes (Algorithm 1: P2M, M2M; Algorithm 3: M2L, L2L)
+// for charges qt in tree order, then L2P at the points (px, py, pz) grouped by
+// leaf as [start[b], start[b+1]) into far[0..3] (allocated here).
+void far_field(const Tree& t, const double* qt, int p, int prec, const int32_t* start, const double* px,
+               const double* py, const double* pz, int64_t npts, double* far[4], hipStream_t s) {
   const int L = t.L;
   PhaseTimer& tm = timer();
-  double* qt = (double*)dalloc(n * sizeof(double), s);
-  k_gather<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(q, t.perm, qt, n);
-  HIPCHECK(hipGetLastError());
+  const Tables& tb = tables_for(p, s);
+  double* Mx = (double*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(double), s);
+  double* Lx = (double*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(double), s);
+  for (int k = 0; k < 4; ++k) far[k] = (double*)dalloc(std::max<int64_t>(1, npts) * sizeof(double), s);
+  tm.begin(FMM_PH_P2M, s);
+  launch_p2m(t, tb, qt, Mx, s);
+  tm.end(FMM_PH_P2M, s);
+  tm.begin(FMM_PH_M2M, s);
+  for (int l = L; l >= 2; --l) launch_m2m(t, l, tb, Mx, s);
+  tm.end(FMM_PH_M2M, s);
+  tm.begin(FMM_PH_M2L, s);
+  launch_m2l(t, tb, Mx, Lx, prec, s);
+  tm.end(FMM_PH_M2L, s);
+  tm.begin(FMM_PH_L2L, s);
+  for (int l = 2; l <= L; ++l) launch_l2l(t, l, tb, Lx, s);
+  tm.end(FMM_PH_L2L, s);
+  tm.begin(FMM_PH_L2P, s);
+  launch_l2p(t, tb, Lx, start, px, py, pz, far[0], far[1], far[2], far[3], s);
+  tm.end(FMM_PH_L2P, s);
+  dfree(Mx, s);
+  dfree(Lx, s);
+}
 
-  double* far[4] = {nullptr, nullptr, nullptr, nullptr};
-  const bool do_far = (parts & FMM_PART_FAR) && L >= 1;
-  if (do_far) {
-    const Tables& tb = tables_for(p, s);
-    double* Mx = (double*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(double), s);
-    double* Lx = (double*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(double), s);
-    for (int k = 0; k < 4; ++k) far[k] = (double*)dalloc(n * sizeof(double), s);
-    tm.begin(FMM_PH_P2M, s);
-    launch_p2m(t, tb, qt, Mx, s);
-    tm.end(FMM_PH_P2M, s);
-    tm.begin(FMM_PH_M2M, s);
-    for (int l = L; l >= 2; --l) launch_m2m(t, l, tb, Mx, s);
-    tm.end(FMM_PH_M2M, s);
-    tm.begin(FMM_PH_M2L, s);
-    launch_m2l(t, tb, Mx, Lx, prec, s);
-    tm.end(FMM_PH_M2L, s);
-    tm.begin(FMM_PH_L2L, s);
-    for (int l = 2; l <= L; ++l) launch_l2l(t, l, tb, Lx, s);
-    tm.end(FMM_PH_L2L, s);
-    tm.begin(FMM_PH_L2P, s);
-    launch_l2p(t, tb, Lx, far[0], far[1], far[2], far[3], s);
-    tm.end(FMM_PH_L2P, s);
-    dfree(Mx, s);
-    dfree(Lx, s);
-  }
-  const Level& V = t.lev[L];
+// Near field (P2P) at the points grouped by leaf as [start[b], start[b+1]) of
+// (px, py, pz), plus the far field when far[0] is set; results go to index
+// perm[.] of the outputs.  leaf_part / npart: partial-sum layout of the split
+// leaves for these points.
+void near_field_and_store(const Tree& t, const double* qt, int parts, const int32_t* start, const double* px,
+                          const double* py, const double* pz, const int32_t* perm, const int64_t* leaf_part,
+                          int64_t npart, double* const far[4], double* pot, double* ex, double* ey, double* ez,
+                          hipStream_t s) {
+  PhaseTimer& tm = timer();
+  const Level& V = t.lev[t.L];
   tm.begin(FMM_PH_P2P, s);
   const unsigned gfin = (unsigned)((V.nbox + 3) / 4);
   if (parts & FMM_PART_NEAR) {
-    double4* part = t.p2p_npart > 0 ? (double4*)dalloc(t.p2p_npart * sizeof(double4), s) : nullptr;
+    double4* part = npart > 0 ? (double4*)dalloc(npart * sizeof(double4), s) : nullptr;
     k_p2p<<<(unsigned)(8 * ((t.p2p_nseg + 7) / 8)), 64, 0, s>>>(
-        t.p2p_nseg, t.p2p_seg_leaf, t.p2p_seg_e0, t.p2p_leaf_seg, t.p2p_leaf_part, V.start, V.s_off, V.s_idx, t.px,
-        t.py, t.pz, qt, t.perm, far[0], far[1], far[2], far[3], part, pot, ex, ey, ez);
+        t.p2p_nseg, t.p2p_seg_leaf, t.p2p_seg_e0, t.p2p_leaf_seg, leaf_part, V.start, V.s_off, V.s_idx, t.px, t.py,
+        t.pz, qt, start, px, py, pz, perm, far[0], far[1], far[2], far[3], part, pot, ex, ey, ez);
     HIPCHECK(hipGetLastError());
     if (part) {
-      k_p2p_final<1><<<gfin, 256, 0, s>>>(V.nbox, V.start, t.p2p_leaf_seg, t.p2p_leaf_part, part, t.perm, far[0],
-                                         far[1], far[2], far[3], pot, ex, ey, ez);
+      k_p2p_final<1><<<gfin, 256, 0, s>>>(V.nbox, start, t.p2p_leaf_seg, leaf_part, part, perm, far[0], far[1],
+                                         far[2], far[3], pot, ex, ey, ez);
       HIPCHECK(hipGetLastError());
       dfree(part, s);
     }
   } else {
-    k_p2p_final<0><<<gfin, 256, 0, s>>>(V.nbox, V.start, nullptr, nullptr, nullptr, t.perm, far[0], far[1], far[2],
+    k_p2p_final<0><<<gfin, 256, 0, s>>>(V.nbox, start, nullptr, nullptr, nullptr, perm, far[0], far[1], far[2],
                                        far[3], pot, ex, ey, ez);
     HIPCHECK(hipGetLastError());
   }
   tm.end(FMM_PH_P2P, s);
+}
+
+double* gather_charges(const Tree& t, const double* q, hipStream_t s) {
+  double* qt = (double*)dalloc(t.n * sizeof(double), s);
+  k_gather<<<(unsigned)((t.n + 255) / 256), 256, 0, s>>>(q, t.perm, qt, t.n);
+  HIPCHECK(hipGetLastError());
+  return qt;
+}
+
+}  // namespace
+
+void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey,
+              double* ez, hipStream_t s) {
+  double* qt = gather_charges(t, q, s);
+  double* far[4] = {nullptr, nullptr, nullptr, nullptr};
+  const Level& V = t.lev[t.L];
+  if ((parts & FMM_PART_FAR) && t.L >= 1) far_field(t, qt, p, prec, V.start, t.px, t.py, t.pz, t.n, far, s);
+  near_field_and_store(t, qt, parts, V.start, t.px, t.py, t.pz, t.perm, t.p2p_leaf_part, t.p2p_npart, far, pot, ex,
+                       ey, ez, s);
+  for (int k = 0; k < 4; ++k)
+    if (far[k]) dfree(far[k], s);
+  dfree(qt, s);
+}
+
+// phi and E at the tree's separate targets (outputs in the caller's target
+// order): the same passes, with L2P and P2P at the targets grouped by leaf
+void evaluate_targets(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey,
+                      double* ez, hipStream_t s) {
+  if (t.m == 0) return;
+  double* qt = gather_charges(t, q, s);
+  double* far[4] = {nullptr, nullptr, nullptr, nullptr};
+  if ((parts & FMM_PART_FAR) && t.L >= 1) far_field(t, qt, p, prec, t.tstart, t.tx, t.ty, t.tz, t.m, far, s);
+  near_field_and_store(t, qt, parts, t.tstart, t.tx, t.ty, t.tz, t.tperm, t.p2p_leaf_tpart, t.p2p_ntpart, far, pot,
+                       ex, ey, ez, s);
   for (int k = 0; k < 4; ++k)
     if (far[k]) dfree(far[k], s);
   dfree(qt, s);

@@ -607,6 +607,145 @@ __global__ __launch_bounds__(64) void k_mb_final(const SegSel* __restrict__ sel,
   seg_n[cb + 1] = n - m;
 }
 
+// ---- eta < 1 (Section 2.1.2): each split plane of a depth moves from the
+// median plane found by the round above to (1 - eta) * (cell midpoint) +
+// eta * (median plane), and the depth's points are partitioned again, stably,
+// by which side of it they lie on (below = low side) ----
+__global__ void k_eta_planes(int64_t nsegd, int depth, double eta, double* __restrict__ cells,
+                             double* __restrict__ plane, int* __restrict__ axis_of) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsegd) return;
+  const int64_t seg = ((int64_t)1 << depth) - 1 + i;
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = cells[seg * 6 + a];
+    hi[a] = cells[seg * 6 + 3 + a];
+  }
+  int axis = 0;
+  double ext = hi[0] - lo[0];
+  if (hi[1] - lo[1] > ext) { ext = hi[1] - lo[1]; axis = 1; }
+  if (hi[2] - lo[2] > ext) { ext = hi[2] - lo[2]; axis = 2; }
+  const int64_t cb = ((int64_t)1 << (depth + 1)) - 1 + 2 * i;
+  const double median = cells[cb * 6 + 3 + axis];
+  const double mid = 0.5 * (lo[axis] + hi[axis]);
+  const double pl = (1.0 - eta) * mid + eta * median;
+  cells[cb * 6 + 3 + axis] = pl;
+  cells[(cb + 1) * 6 + axis] = pl;
+  plane[i] = pl;
+  axis_of[i] = axis;
+}
+
+// per point of the depth's (pre-split) order: its segment (the last one
+// starting at or before it; the segments tile [0, n) in order) and whether it
+// lies below that segment's plane
+__global__ void k_eta_flags(int64_t n, int depth, int64_t nsegd, const int32_t* __restrict__ seg_start,
+                            const double* __restrict__ plane, const int* __restrict__ axis_of,
+                            const double* __restrict__ xin, const double* __restrict__ yin,
+                            const double* __restrict__ zin, int32_t* __restrict__ flag, int32_t* __restrict__ segof) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t* st = seg_start + ((int64_t)1 << depth) - 1;
+  int64_t lo = 0, hi = nsegd - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (st[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  const int a = axis_of[lo];
+  const double c = a == 0 ? xin[i] : (a == 1 ? yin[i] : zin[i]);
+  flag[i] = c < plane[lo] ? 1 : 0;
+  segof[i] = (int32_t)lo;
+}
+
+// stable partition by the flags: low side first, each side in its old order
+__global__ void k_eta_scatter(int64_t n, int depth, const int32_t* __restrict__ seg_start,
+                              const int32_t* __restrict__ seg_n, const int32_t* __restrict__ segof,
+                              const int32_t* __restrict__ flag, const int64_t* __restrict__ below,
+                              const double* __restrict__ xin, const double* __restrict__ yin,
+                              const double* __restrict__ zin, const int32_t* __restrict__ iin,
+                              double* __restrict__ xout, double* __restrict__ yout, double* __restrict__ zout,
+                              int32_t* __restrict__ iout) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t seg = ((int64_t)1 << depth) - 1 + segof[i];
+  const int64_t st = seg_start[seg], ns = seg_n[seg];
+  const int64_t b = below[i] - below[st];
+  const int64_t nlow = below[st + ns] - below[st];
+  const int64_t dst = flag[i] ? st + b : st + nlow + (i - st - b);
+  xout[dst] = xin[i];
+  yout[dst] = yin[i];
+  zout[dst] = zin[i];
+  iout[dst] = iin[i];
+}
+
+__global__ void k_eta_counts(int64_t nsegd, int depth, const int64_t* __restrict__ below,
+                             int32_t* __restrict__ seg_start, int32_t* __restrict__ seg_n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsegd) return;
+  const int64_t seg = ((int64_t)1 << depth) - 1 + i;
+  const int32_t st = seg_start[seg], ns = seg_n[seg];
+  const int32_t nlow = (int32_t)(below[st + ns] - below[st]);
+  const int64_t cb = ((int64_t)1 << (depth + 1)) - 1 + 2 * i;
+  seg_start[cb] = st;
+  seg_n[cb] = nlow;
+  seg_start[cb + 1] = st + nlow;
+  seg_n[cb + 1] = ns - nlow;
+}
+
+// ---- separate targets: the leaf whose cell holds each target (from the
+// root, the first of the eight children in child order whose closed cell
+// contains it), then the targets grouped by leaf ----
+__global__ void k_locate(int64_t m, LevelView lv, const double* __restrict__ tx, const double* __restrict__ ty,
+                         const double* __restrict__ tz, int32_t* __restrict__ tleaf, int* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const double v[3] = {tx[k], ty[k], tz[k]};
+  int64_t b = 0;
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) ok = ok && v[a] >= lv.geom[0][a] && v[a] <= lv.geom[0][3 + a];
+  for (int l = 1; l <= lv.L && ok; ++l) {
+    const double* g = lv.geom[l];
+    int64_t found = -1;
+    for (int c = 0; c < 8 && found < 0; ++c) {
+      const int64_t j = 8 * b + c;
+      bool in = true;
+      for (int a = 0; a < 3; ++a) in = in && v[a] >= g[j * 10 + a] && v[a] <= g[j * 10 + 3 + a];
+      if (in) found = j;
+    }
+    if (found < 0) ok = false;
+    else b = found;
+  }
+  if (!ok) atomicOr(bad, 1);
+  tleaf[k] = ok ? (int32_t)b : 0;
+}
+
+__global__ void k_tcount(int64_t m, const int32_t* __restrict__ tleaf, int32_t* __restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) atomicAdd(&cnt[tleaf[k]], 1);
+}
+
+// targets into their leaf's range; the order inside a leaf is not fixed
+// (every target's result depends only on its own position and leaf)
+__global__ void k_tscatter(int64_t m, const int32_t* __restrict__ tleaf, const int64_t* __restrict__ off,
+                           int32_t* __restrict__ cursor, const double* __restrict__ tx, const double* __restrict__ ty,
+                           const double* __restrict__ tz, double* __restrict__ gx, double* __restrict__ gy,
+                           double* __restrict__ gz, int32_t* __restrict__ tperm) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int32_t b = tleaf[k];
+  const int64_t dst = off[b] + atomicAdd(&cursor[b], 1);
+  gx[dst] = tx[k];
+  gy[dst] = ty[k];
+  gz[dst] = tz[k];
+  tperm[dst] = (int32_t)k;
+}
+
+__global__ void k_to_int32(int64_t n, const int64_t* __restrict__ in, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) out[i] = (int32_t)in[i];
+}
+
 // centre = cell centre, radius = half the cell diagonal (Section 2.1.1)
 __global__ void k_box_geom(const double* __restrict__ cells, const int32_t* __restrict__ seg_start, int depth,
                            int64_t nbox, double* __restrict__ geom, int32_t* __restrict__ start, int32_t n) {
@@ -632,7 +771,8 @@ __global__ void k_box_geom(const double* __restrict__ cells, const int32_t* __re
 
 }  // namespace
 
-void tree_build(Tree& t, const double* x, const double* y, const double* z, hipStream_t s) {
+void tree_build(Tree& t, const double* x, const double* y, const double* z, const double* tx, const double* ty,
+                const double* tz, hipStream_t s) {
   const int64_t n = t.n;
   const int L = t.L;
   double* xs[2];
@@ -656,12 +796,34 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, hipS
   k_canon_copy<<<nb, 256, 0, s>>>(x, y, z, xs[0], ys[0], zs[0], ids[0], n, bad);
   HIPCHECK(hipGetLastError());
   const int nparts = (int)std::min<int64_t>(1024, (n + 255) / 256);
-  double* part = (double*)dalloc((size_t)nparts * 6 * sizeof(double), s);
+  const int64_t m = t.m;
+  const int nparts_t = m > 0 ? (int)std::min<int64_t>(1024, (m + 255) / 256) : 0;
+  double* part = (double*)dalloc((size_t)(nparts + nparts_t) * 6 * sizeof(double), s);
   k_bbox_partial<<<nparts, 256, 0, s>>>(xs[0], ys[0], zs[0], n, part);
   HIPCHECK(hipGetLastError());
-  k_bbox_final<<<1, 64, 0, s>>>(part, nparts, n, cells, seg_start, seg_n);
+  if (m > 0) {
+    // canonical copies of the targets (caller's order); they widen the root
+    int32_t* tid = (int32_t*)dalloc(m * sizeof(int32_t), s);
+    t.tx = (double*)dalloc(m * sizeof(double), s);
+    t.ty = (double*)dalloc(m * sizeof(double), s);
+    t.tz = (double*)dalloc(m * sizeof(double), s);
+    k_canon_copy<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(tx, ty, tz, t.tx, t.ty, t.tz, tid, m, bad);
+    HIPCHECK(hipGetLastError());
+    dfree(tid, s);
+    k_bbox_partial<<<nparts_t, 256, 0, s>>>(t.tx, t.ty, t.tz, m, part + (size_t)nparts * 6);
+    HIPCHECK(hipGetLastError());
+  }
+  k_bbox_final<<<1, 64, 0, s>>>(part, nparts + nparts_t, n, cells, seg_start, seg_n);
   HIPCHECK(hipGetLastError());
   dfree(part, s);
+  // eta < 1: per-depth plane and segment scratch for the re-partition
+  const bool blend = t.eta < 1.0;
+  const int64_t maxsegd = L > 0 ? ((int64_t)1 << (3 * L - 1)) : 1;
+  double* eplane = blend ? (double*)dalloc(maxsegd * sizeof(double), s) : nullptr;
+  int* eaxis = blend ? (int*)dalloc(maxsegd * sizeof(int), s) : nullptr;
+  int32_t* eflag = blend ? (int32_t*)dalloc(n * sizeof(int32_t), s) : nullptr;
+  int32_t* esegof = blend ? (int32_t*)dalloc(n * sizeof(int32_t), s) : nullptr;
+  int64_t* ebelow = blend ? (int64_t*)dalloc((n + 1) * sizeof(int64_t), s) : nullptr;
 
   // rounds whose segments all hold at least kMultiMin points (and are few)
   // go through the chunked kernels; the rest run one block per segment
@@ -672,7 +834,11 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, hipS
   int2* ccount = nullptr;
   int2* cbase = nullptr;
   double2* cpart = nullptr;
-  if (n / 2 >= kMultiMin) {
+  // the chunked rounds' state, allocated under the condition that selects
+  // them below: a round is chunked when every segment holds at least
+  // kMultiMin points, the first one (a single segment) when n >= kMultiMin
+  const bool any_multi = !blend && n >= kMultiMin;
+  if (any_multi) {
     const int64_t nblk = (n + kChunk - 1) / kChunk + kMultiMaxSeg;  // chunks of any multi-block round
     sel = (SegSel*)dalloc(kMultiMaxSeg * sizeof(SegSel), s);
     ghist = (unsigned*)dalloc(kMultiMaxSeg * 256 * sizeof(unsigned), s);
@@ -687,7 +853,7 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, hipS
     const int64_t maxn = (n + nsegd - 1) / nsegd;
     const int64_t minn = n / nsegd;
     const int o = cur ^ 1;
-    if (minn >= kMultiMin && nsegd <= kMultiMaxSeg) {
+    if (any_multi && minn >= kMultiMin && nsegd <= kMultiMaxSeg) {
       const int nchunk = (int)((maxn + kChunk - 1) / kChunk);
       const unsigned nseg = (unsigned)nsegd, nblk = (unsigned)(nsegd * nchunk);
       k_mb_init<<<nseg, 256, 0, s>>>(cells, seg_n, depth, sel, ghist);
@@ -707,7 +873,7 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, hipS
       HIPCHECK(hipGetLastError());
       k_mb_final<<<nseg, 64, 0, s>>>(sel, nchunk, cpart, cells, seg_start, seg_n, depth);
       HIPCHECK(hipGetLastError());
-    } else if (maxn > 128) {
+    } else if (blend || maxn > 128) {
       k_orb_round<256><<<(unsigned)nsegd, 256, 0, s>>>(xs[cur], ys[cur], zs[cur], ids[cur], xs[o], ys[o], zs[o],
                                                        ids[o], cells, seg_start, seg_n, depth);
     } else {
@@ -715,7 +881,28 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, hipS
                                                      ids[o], cells, seg_start, seg_n, depth);
     }
     HIPCHECK(hipGetLastError());
+    if (blend) {
+      const unsigned gs = (unsigned)((nsegd + 255) / 256), gp = (unsigned)((n + 255) / 256);
+      k_eta_planes<<<gs, 256, 0, s>>>(nsegd, depth, t.eta, cells, eplane, eaxis);
+      HIPCHECK(hipGetLastError());
+      k_eta_flags<<<gp, 256, 0, s>>>(n, depth, nsegd, seg_start, eplane, eaxis, xs[cur], ys[cur], zs[cur], eflag,
+                                     esegof);
+      HIPCHECK(hipGetLastError());
+      scan_counts(eflag, ebelow, n, 0, s);
+      k_eta_scatter<<<gp, 256, 0, s>>>(n, depth, seg_start, seg_n, esegof, eflag, ebelow, xs[cur], ys[cur], zs[cur],
+                                       ids[cur], xs[o], ys[o], zs[o], ids[o]);
+      HIPCHECK(hipGetLastError());
+      k_eta_counts<<<gs, 256, 0, s>>>(nsegd, depth, ebelow, seg_start, seg_n);
+      HIPCHECK(hipGetLastError());
+    }
     cur = o;
+  }
+  if (blend) {
+    dfree(eplane, s);
+    dfree(eaxis, s);
+    dfree(eflag, s);
+    dfree(esegof, s);
+    dfree(ebelow, s);
   }
   if (sel) {
     dfree(sel, s);
@@ -756,6 +943,52 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, hipS
   HIPCHECK(hipStreamSynchronize(s));
   dfree(bad, s);
   if (hbad) fail(FMM_EINVAL, "non-finite coordinate or |coordinate| > 1e300");
+}
+
+void targets_build(Tree& t, hipStream_t s) {
+  const int64_t m = t.m;
+  const int L = t.L;
+  const int64_t nleaf = t.lev[L].nbox;
+  t.tleaf = (int32_t*)dalloc(std::max<int64_t>(1, m) * sizeof(int32_t), s);
+  t.tstart = (int32_t*)dalloc((nleaf + 1) * sizeof(int32_t), s);
+  int* bad = (int*)dalloc(sizeof(int), s);
+  int32_t* cnt = (int32_t*)dalloc(nleaf * sizeof(int32_t), s);
+  int64_t* off = (int64_t*)dalloc((nleaf + 1) * sizeof(int64_t), s);
+  HIPCHECK(hipMemsetAsync(bad, 0, sizeof(int), s));
+  HIPCHECK(hipMemsetAsync(cnt, 0, nleaf * sizeof(int32_t), s));
+  const unsigned gm = (unsigned)((m + 255) / 256);
+  if (m > 0) {
+    k_locate<<<gm, 256, 0, s>>>(m, t.view(), t.tx, t.ty, t.tz, t.tleaf, bad);
+    HIPCHECK(hipGetLastError());
+    k_tcount<<<gm, 256, 0, s>>>(m, t.tleaf, cnt);
+    HIPCHECK(hipGetLastError());
+  }
+  scan_counts(cnt, off, nleaf, 0, s);
+  k_to_int32<<<(unsigned)((nleaf + 1 + 255) / 256), 256, 0, s>>>(nleaf, off, t.tstart);
+  HIPCHECK(hipGetLastError());
+  double* gx = (double*)dalloc(std::max<int64_t>(1, m) * sizeof(double), s);
+  double* gy = (double*)dalloc(std::max<int64_t>(1, m) * sizeof(double), s);
+  double* gz = (double*)dalloc(std::max<int64_t>(1, m) * sizeof(double), s);
+  t.tperm = (int32_t*)dalloc(std::max<int64_t>(1, m) * sizeof(int32_t), s);
+  if (m > 0) {
+    HIPCHECK(hipMemsetAsync(cnt, 0, nleaf * sizeof(int32_t), s));
+    k_tscatter<<<gm, 256, 0, s>>>(m, t.tleaf, off, cnt, t.tx, t.ty, t.tz, gx, gy, gz, t.tperm);
+    HIPCHECK(hipGetLastError());
+  }
+  dfree(t.tx, s);
+  dfree(t.ty, s);
+  dfree(t.tz, s);
+  t.tx = gx;
+  t.ty = gy;
+  t.tz = gz;
+  dfree(cnt, s);
+  dfree(off, s);
+  int hbad = 0;
+  HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  dfree(bad, s);
+  // every target lies in the root cell, which is widened to hold them
+  if (hbad) fail(FMM_EDEVICE, "a target was not found in any leaf cell");
 }
 
 }  // namespace fmm

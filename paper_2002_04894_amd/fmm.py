@@ -45,6 +45,9 @@ def lib():
     L.fmm_evaluate_tree_parts.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
     L.fmm_evaluate_tree_ex.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]
     L.fmm_evaluate.argtypes = [vp, vp, vp, vp, i64, d, i32, i32, vp, vp, vp, vp, vp]
+    L.fmm_build_ex.argtypes = [vp, vp, vp, i64, vp, vp, vp, i64, i32, d, d, vp, C.POINTER(vp)]
+    L.fmm_evaluate_targets.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]
+    L.fmm_tree_targets.argtypes = [vp, C.POINTER(i64), vp]
     L.fmm_free.argtypes = [vp]
     L.fmm_last_error.argtypes = []
     L.fmm_last_error.restype = C.c_char_p
@@ -57,7 +60,8 @@ def lib():
     L.fmm_last_timings.argtypes = [vp]
     L.fmm_bytes_estimate.argtypes = [i64, i32, d, i32]
     L.fmm_bytes_estimate.restype = C.c_size_t
-    for f in ("fmm_build", "fmm_evaluate_tree", "fmm_evaluate_tree_parts", "fmm_evaluate", "fmm_free",
+    for f in ("fmm_build", "fmm_build_ex", "fmm_evaluate_targets", "fmm_tree_targets", "fmm_evaluate_tree_ex",
+              "fmm_evaluate_tree", "fmm_evaluate_tree_parts", "fmm_evaluate", "fmm_free",
               "fmm_tree_info", "fmm_tree_perm", "fmm_tree_boxes", "fmm_tree_lists", "fmm_tree_stats",
               "fmm_set_profiling", "fmm_last_timings"):
         getattr(L, f).restype = i32
@@ -93,11 +97,12 @@ def _stream(stream):
 
 
 class Tree:
-    """Owning wrapper of an fmm_tree handle."""
+    """Owning wrapper of an fmm_tree handle (n sources, m separate targets)."""
 
-    def __init__(self, handle: int, n: int):
+    def __init__(self, handle: int, n: int, m: int = 0):
         self.handle = handle
         self.n = n
+        self.m = m
 
     def free(self):
         if self.handle:
@@ -118,6 +123,47 @@ def fmm_build(x, y, z, levels: int, theta: float, stream=None) -> Tree:
     _check(lib().fmm_build(_ptr(x), _ptr(y), _ptr(z), x.numel(), int(levels), float(theta), _stream(stream),
                            C.byref(h)))
     return Tree(h.value, x.numel())
+
+
+def fmm_build_ex(x, y, z, levels: int, theta: float, eta: float = 1.0, targets=None, stream=None) -> Tree:
+    """Tree with split parameter eta and optional separate targets (tx, ty, tz)."""
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _dev(t, nm)
+    if targets is None:
+        tp, m = (None, None, None), 0
+    else:
+        for t, nm in zip(targets, ("tx", "ty", "tz")):
+            _dev(t, nm)
+        m = targets[0].numel()
+        if any(t.numel() != m for t in targets):
+            raise ValueError("tx, ty, tz must have the same length")
+        tp = tuple(_ptr(t) for t in targets)
+    h = C.c_void_p()
+    _check(lib().fmm_build_ex(_ptr(x), _ptr(y), _ptr(z), x.numel(), *tp, m, int(levels), float(theta), float(eta),
+                              _stream(stream), C.byref(h)))
+    return Tree(h.value, x.numel(), m)
+
+
+def fmm_evaluate_targets(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts: int = FMM_PART_ALL,
+                         precision: int = FMM_PREC_F64):
+    _dev(q, "q")
+    if q.numel() != tree.n:
+        raise ValueError(f"q must have {tree.n} elements")
+    for t, nm in ((pot, "pot"), (ex, "ex"), (ey, "ey"), (ez, "ez")):
+        _dev(t, nm)
+        if t.numel() != tree.m:
+            raise ValueError(f"{nm} must have {tree.m} elements")
+    _check(lib().fmm_evaluate_targets(tree.handle, _ptr(q), int(p), int(parts), int(precision), _ptr(pot), _ptr(ex),
+                                      _ptr(ey), _ptr(ez), _stream(stream)))
+
+
+def fmm_tree_targets(tree: Tree) -> np.ndarray:
+    """Leaf of each separate target (caller's order)."""
+    m = C.c_int64()
+    _check(lib().fmm_tree_targets(tree.handle, C.byref(m), None))
+    leaf = np.empty(max(m.value, 1), dtype=np.int32)
+    _check(lib().fmm_tree_targets(tree.handle, C.byref(m), leaf.ctypes.data))
+    return leaf[: m.value]
 
 
 def fmm_evaluate_tree(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts: int = FMM_PART_ALL,

@@ -276,6 +276,21 @@ def test_full_size_gmix1m_sampled(torch, F, orc):
     gt.free()
 
 
+@pytest.mark.parametrize("n,L", [(8192, 2), (8300, 3), (12000, 2), (16383, 2)])
+def test_parity_sizes_with_one_chunked_round(torch, F, orc, n, L):
+    """8192 <= n < 16384 source points: only the first bisection round (one
+    segment of n points) runs as chunked blocks.  Its state must be allocated
+    for that round too (it once was not, and such builds took a GPU memory
+    fault); tree bit for bit and values against the oracle."""
+    say(f"[sizes] uniform n={n} L={L}")
+    x, y, z, q = W.uniform_cube(n, seed=n)
+    ot = orc.Tree(x, y, z, L, 0.5)
+    gt = gpu_tree(torch, F, x, y, z, L, 0.5)
+    assert_tree_equal(F, gt, ot, L)
+    assert_close(gpu_eval(torch, F, gt, q, 4), ot.evaluate(q, 4), what=f"n={n}")
+    gt.free()
+
+
 @pytest.mark.parametrize("p", [16, 19])
 def test_parity_first_use_on_side_stream(torch, F, orc, p):
     """Orders that no other test here evaluates, so that their operator
@@ -299,9 +314,6 @@ def test_parity_first_use_on_side_stream(torch, F, orc, p):
     assert_close(got, ot.evaluate(q, p), what=f"side stream p={p}")
 
 
-@pytest.mark.skip(reason="a GPU memory fault in this test's serial phase (18 solves in a row on one "
-                         "non-blocking stream, orders 3..20, both precisions) is not yet explained; kept "
-                         "off the GPU until its cause is shown")
 def test_threads_on_own_streams_match_serial(torch, F):
     """Host threads, each with its own non-blocking stream, build and evaluate
     at the same time (orders on both sides of the MFMA limit, both

@@ -78,8 +78,6 @@ def test_admission_respects_budget(monkeypatch):
 
 
 @pytest.mark.gpu
-@pytest.mark.skip(reason="the serving run (calibration, then a request stream over six worker streams) took "
-                         "a GPU memory fault whose cause is not yet shown; kept off the GPU until it is")
 def test_results_same_alone_and_in_the_mix():
     import torch
     if not torch.cuda.is_available():
@@ -97,10 +95,3 @@ def test_results_same_alone_and_in_the_mix():
         for u, v in zip(a.outputs, m.outputs):
             assert np.array_equal(u, v)
 
-
-def test_device_path_switched_off():
-    """While the serving fault is unexplained, the device entry points raise."""
-    with pytest.raises(RuntimeError):
-        serve.Tuner().calibrate()
-    with pytest.raises(RuntimeError):
-        serve.Server(serve.Tuner(c=1e-3)).solve(serve.Request(0, 0.0, "uniform", 100, 1e-4, 1), None, None)
