@@ -13,10 +13,11 @@ The tuner picks (levels, theta, p, precision) per request:
   * levels: about kPointsPerLeaf points per leaf (8^levels leaves);
   * theta: fixed (the paper's optimum lies near 0.5 for these distributions,
     Section 3.2);
-  * p: the smallest order whose modelled error C * theta^(p+1) (the
-    convergence bound of Section 3.1) is below the requested accuracy, with C
-    calibrated on the GPU against direct sums (a theta = 0 tree is the
-    direct sum) on sample clouds of the served distributions;
+  * p: the smallest order whose modelled error is below the requested
+    accuracy, the model being the worst error measured on the GPU against
+    direct sums (a theta = 0 tree is the direct sum) on sample clouds of the
+    served distributions at orders 1..16, extended geometrically in p (the
+    convergence of Section 3.1);
   * precision: the mixed mode (binary32 M2L) when the requested accuracy is
     1e-6 or looser, binary64 otherwise.
 
@@ -98,14 +99,22 @@ def direct_sum(x, y, z, q, stream=None):
 
 
 class Tuner:
-    """Parameter choice from (n, tol); see the module docstring."""
+    """Parameter choice from (n, tol); see the module docstring.
+
+    The expansion order comes from measured errors: errors[p] is the largest
+    relative error (potential or field) of the FMM against the direct sum at
+    order p over calibration clouds of the served distributions.  Between and
+    beyond the calibrated orders the error is extended geometrically (the
+    convergence of Section 3.1 is geometric in p), and the model is made
+    non-increasing in p.  The order for an accuracy tol is the smallest p with
+    kSafety * model(p) <= tol, else pmax."""
 
     kPointsPerLeaf = 40.0
     kSafety = 2.0
 
-    def __init__(self, theta: float = 0.5, c: float | None = None, pmax: int = fmm.FMM_MAX_ORDER):
+    def __init__(self, theta: float = 0.5, errors: dict | None = None, pmax: int = fmm.FMM_MAX_ORDER):
         self.theta = theta
-        self.c = c  # error constant of the model C * theta^(p+1)
+        self.errors = dict(errors) if errors else None
         self.pmax = pmax
 
     def levels(self, n: int) -> int:
@@ -113,11 +122,33 @@ class Tuner:
             return 0
         return int(min(fmm.FMM_MAX_LEVELS, max(0, round(math.log(n / self.kPointsPerLeaf, 8)))))
 
-    def order(self, tol: float) -> int:
-        if self.c is None:
+    def _raw(self, p: int) -> float:
+        ps = sorted(self.errors)
+        if p in self.errors:
+            return self.errors[p]
+        if len(ps) == 1:
+            return self.errors[ps[0]] if p > ps[0] else math.inf
+        # geometric inter- or extrapolation between the two nearest calibrated orders
+        if p < ps[0]:
+            a, b = ps[0], ps[1]
+        elif p > ps[-1]:
+            a, b = ps[-2], ps[-1]
+        else:
+            b = next(q for q in ps if q > p)
+            a = max(q for q in ps if q < p)
+        ea, eb = max(self.errors[a], 1e-300), max(self.errors[b], 1e-300)
+        rate = (eb / ea) ** (1.0 / (b - a))
+        return ea * rate ** (p - a)
+
+    def model(self, p: int) -> float:
+        """Modelled worst error at order p: non-increasing in p."""
+        if self.errors is None:
             raise RuntimeError("the tuner is not calibrated")
+        return max(self._raw(q) for q in range(p, self.pmax + 1))
+
+    def order(self, tol: float) -> int:
         for p in range(self.pmax + 1):
-            if self.kSafety * self.c * self.theta ** (p + 1) <= tol:
+            if self.kSafety * self.model(p) <= tol:
                 return p
         return self.pmax
 
@@ -126,13 +157,13 @@ class Tuner:
         prec = fmm.FMM_PREC_MIXED if (tol >= 1e-6 and p <= 15) else fmm.FMM_PREC_F64
         return self.levels(n), self.theta, p, prec
 
-    def calibrate(self, n: int = 20_000, orders=range(2, 15, 2), seed: int = 7, stream=None) -> dict:
-        """Fit C on the GPU: relative error (normwise, potential and field,
-        the larger) of the FMM against the direct sum for each distribution and
-        order; C is the largest err / theta^(p+1) seen."""
+    def calibrate(self, n: int = 20_000, orders=range(1, 17), seed: int = 7, stream=None) -> dict:
+        """Measure errors[p] on the GPU: relative error (normwise, potential
+        and field, the larger) of the FMM against the direct sum, the largest
+        over the served distributions."""
         import torch
-        worst = 0.0
         table = {}
+        worst: dict[int, float] = {}
         for dist in DISTRIBUTIONS:
             req = Request(-1, 0.0, dist, n, 0.0, seed)
             x, y, z, q = request_points(req)
@@ -149,9 +180,9 @@ class Tuner:
                 den = sum(float(torch.sum(b ** 2)) for b in ref[1:])
                 err = max(e_phi, math.sqrt(num / den))
                 table[(dist, p)] = err
-                worst = max(worst, err / self.theta ** (p + 1))
+                worst[p] = max(worst.get(p, 0.0), err)
             tree.free()
-        self.c = worst
+        self.errors = worst
         return table
 
 
@@ -297,7 +328,8 @@ def run_stream(nreq: int = 4000, rate: float = 200.0, workers: int = 6, check_ev
     out = summary(results, reqs)
     out.update({"workers": workers, "hbm_budget_gb": round(hbm_budget / 2 ** 30, 1),
                 "peak_concurrency": srv.peak_concurrency, "peak_bytes_gb": round(srv.peak_bytes / 1e9, 3),
-                "tuner_c": tuner.c, "calibration_s": round(cal_s, 2)})
+                "tuner_errors": {p: float(f"{e:.3g}") for p, e in sorted(tuner.errors.items())},
+                "orders": {str(t): tuner.order(t) for t in (1e-4, 1e-8)}, "calibration_s": round(cal_s, 2)})
     checks = []
     stream = torch.cuda.Stream()
     keep = Server(tuner, workers=1, keep_outputs=True)

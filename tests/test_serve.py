@@ -29,22 +29,46 @@ def test_stream_recipe():
     assert [(r.arrival, r.n, r.dist, r.tol) for r in again] == [(r.arrival, r.n, r.dist, r.tol) for r in reqs]
 
 
+SYNTH = {p: 1e-3 * 0.5 ** p for p in range(1, 17)}  # errors halving per order
+
+
 def test_tuner_rules():
-    t = serve.Tuner(theta=0.5, c=1e-3)
+    t = serve.Tuner(theta=0.5, errors=SYNTH)
     # levels: about 40 points per leaf
     assert t.levels(30) == 0
     assert t.levels(320) == 1
     assert t.levels(20_000) == 3
     assert t.levels(10 ** 9) == 8
-    # the order is the smallest with 2 C theta^(p+1) <= tol
-    for tol in (1e-2, 1e-4, 1e-6, 1e-8):
+    # calibrated orders: the model is the measurement; the order is the
+    # smallest with 2 * model <= tol
+    for p in range(1, 17):
+        assert t.model(p) == SYNTH[p]
+    for tol in (1e-2, 1e-4, 1e-6):
         p = t.order(tol)
-        assert 2 * t.c * 0.5 ** (p + 1) <= tol
-        assert p == 0 or 2 * t.c * 0.5 ** p > tol
-    assert t.order(1e-4) < t.order(1e-8)
+        assert 2 * t.model(p) <= tol and (p == 0 or 2 * t.model(p - 1) > tol)
+    # beyond the calibrated orders: geometric extension at the last rate
+    assert np.isclose(t.model(18), SYNTH[16] * 0.25, rtol=1e-12)
+    assert np.isclose(t.model(0), SYNTH[1] * 2.0, rtol=1e-12)
+    assert t.order(1e-8) == 18
+    # unreachable accuracy: the largest order
+    assert t.order(1e-30) == t.pmax
+    # mixed precision for 1e-6 and looser at p <= 15
     assert t.choose(5000, 1e-4)[3] == 1 and t.choose(5000, 1e-8)[3] == 0
     with pytest.raises(RuntimeError):
         serve.Tuner().order(1e-4)
+
+
+def test_tuner_model_is_monotone():
+    """A measurement that rises with p (noise, or the rounding floor) must
+    not let the tuner pick the lower order."""
+    e = dict(SYNTH)
+    e[10] = 1e-5  # larger than e[8] = 3.9e-6
+    t = serve.Tuner(errors=e)
+    assert t.model(8) >= 1e-5 and t.model(9) >= 1e-5
+    assert all(t.model(p) >= t.model(p + 1) for p in range(0, 20))
+    # without the correction order 8 would pass (2 * 3.9e-6 <= 1.5e-5) although
+    # order 10 measured 1e-5; with it the first order past the bump is chosen
+    assert t.order(1.5e-5) == 11
 
 
 class FakeServer(serve.Server):
@@ -68,7 +92,7 @@ def test_admission_respects_budget(monkeypatch):
     fake_torch = types.SimpleNamespace(cuda=FakeCuda)
     monkeypatch.setitem(__import__("sys").modules, "torch", fake_torch)
     reqs = [serve.Request(i, 0.0, "uniform", 100 + 50 * (i % 5), 1e-4, i) for i in range(60)]
-    srv = FakeServer(serve.Tuner(c=1e-3), workers=6, hbm_budget=500)
+    srv = FakeServer(serve.Tuner(errors=SYNTH), workers=6, hbm_budget=500)
     res = srv.run(reqs, realtime=False)
     assert sorted(r.rid for r in res) == list(range(60))
     assert all(not r.error for r in res)
@@ -85,7 +109,7 @@ def test_results_same_alone_and_in_the_mix():
     rng = np.random.default_rng(11)
     reqs = [serve.Request(i, 0.0, serve.DISTRIBUTIONS[i % 3], int(rng.integers(1000, 30_000)),
                           (1e-4, 1e-8)[i % 2], 5000 + i) for i in range(24)]
-    tuner = serve.Tuner(c=1e-3)
+    tuner = serve.Tuner(errors=SYNTH)  # p 5 (mixed) for 1e-4, p 18 (binary64) for 1e-8
     mixed = serve.Server(tuner, workers=6, keep_outputs=True).run(reqs, realtime=False)
     alone = serve.Server(tuner, workers=1, keep_outputs=True)
     stream = torch.cuda.Stream()
