@@ -46,7 +46,7 @@ enum fmm_status {
   FMM_EINVAL = -1,       /* invalid argument (NULL pointer, range, non-finite coordinate) */
   FMM_ENOMEM = -2,       /* device or host allocation failed */
   FMM_EDEVICE = -3,      /* HIP runtime error (no device, launch failure, ...) */
-  FMM_EUNSUPPORTED = -4  /* valid request this build does not support */
+  FMM_EUNSUPPORTED = -4  /* valid request that the library does not support */
 };
 
 #define FMM_MAX_LEVELS 8

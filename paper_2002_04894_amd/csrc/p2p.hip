@@ -48,7 +48,7 @@ __device__ __forceinline__ int64_t xcd_leaf(int64_t nleaf) {
   return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-constexpr int kP2PBuf = 512;     // source points staged per chunk (x, y, z, q)
+constexpr int kP2PBuf = 256;     // source points staged per chunk (x, y, z, q): 8 KB of LDS, 3 waves per SIMD
 constexpr int64_t kP2PSeg = 8192;  // source points per work item (about)
 
 // ---- the plan: one wave per leaf walks its strong list 64 entries at a

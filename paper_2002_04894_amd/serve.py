@@ -10,16 +10,15 @@ result depends only on its own data and parameters (the solver is
 deterministic), so it is the same alone and in the mix.
 
 The tuner picks (levels, theta, p, precision) per request:
-  * levels: about kPointsPerLeaf points per leaf (8^levels leaves);
-  * theta: fixed (the paper's optimum lies near 0.5 for these distributions,
-    Section 3.2);
-  * p: the smallest order whose modelled error is below the requested
-    accuracy, the model being the worst error measured on the GPU against
-    direct sums (a theta = 0 tree is the direct sum) on sample clouds of the
-    served distributions at orders 1..16, extended geometrically in p (the
-    convergence of Section 3.1);
-  * precision: the mixed mode (binary32 M2L) when the requested accuracy is
-    1e-6 or looser, binary64 otherwise.
+  * levels: about kPointsPerLeaf points per leaf (8^levels leaves), a priori;
+  * theta, p and precision: the cheapest combination, by the evaluation time
+    per point measured on the GPU, whose modelled error times a safety factor
+    meets the requested accuracy.  The error model is the worst error
+    measured against direct sums (a theta = 0 tree is the direct sum) on
+    sample clouds of the served distributions, per level count and theta, at
+    orders 1..16, extended geometrically in p (the convergence of Section
+    3.1).  Mixed precision (binary32 M2L) is a candidate for accuracies of
+    1e-6 and looser.
 
 The device work goes through the C ABI (`fmm.py`); nothing here computes.
 """
@@ -101,34 +100,62 @@ def direct_sum(x, y, z, q, stream=None):
 class Tuner:
     """Parameter choice from (n, tol); see the module docstring.
 
-    The expansion order comes from measured errors: errors[p] is the largest
-    relative error (potential or field) of the FMM against the direct sum at
-    order p over calibration clouds of the served distributions.  Between and
-    beyond the calibrated orders the error is extended geometrically (the
-    convergence of Section 3.1 is geometric in p), and the model is made
-    non-increasing in p.  The order for an accuracy tol is the smallest p with
-    kSafety * model(p) <= tol, else pmax."""
+    levels: about kPointsPerLeaf points per leaf (fixed a priori, as the
+    paper advises).  theta, p and the precision: the cheapest choice whose
+    modelled error meets the accuracy with a safety factor, from a table
+    measured on the GPU (`calibrate`) for each level count and theta:
+    errors[(L, theta)][p] is the worst relative error (potential or field)
+    against the direct sum over sample clouds of the served distributions,
+    cost[(L, theta, prec)][p] the measured evaluation time per point.  In p
+    the errors are extended geometrically (the convergence of Section 3.1 is
+    geometric in p) and made non-increasing; costs beyond the measured orders
+    grow like (p+1)^3.  A level count that was not calibrated uses the worst
+    calibrated one at or above it (deeper trees carry larger errors), else the
+    deepest."""
 
     kPointsPerLeaf = 40.0
     kSafety = 2.0
+    kMixedMinTol = 1e-6  # mixed precision adds about 1e-7 relative error
 
-    def __init__(self, theta: float = 0.5, errors: dict | None = None, pmax: int = fmm.FMM_MAX_ORDER):
+    def __init__(self, theta: float = 0.5, errors: dict | None = None, cost: dict | None = None,
+                 pmax: int = fmm.FMM_MAX_ORDER):
         self.theta = theta
-        self.errors = dict(errors) if errors else None
         self.pmax = pmax
+        # errors: {(L, theta): {p: err}}; a plain {p: err} applies to every L at `theta`
+        if errors and all(isinstance(k, int) for k in errors):
+            errors = {(None, theta): dict(errors)}
+        self.errors = {k: dict(v) for k, v in errors.items()} if errors else None
+        self.cost = {k: dict(v) for k, v in cost.items()} if cost else {}
 
     def levels(self, n: int) -> int:
         if n <= self.kPointsPerLeaf:
             return 0
         return int(min(fmm.FMM_MAX_LEVELS, max(0, round(math.log(n / self.kPointsPerLeaf, 8)))))
 
-    def _raw(self, p: int) -> float:
-        ps = sorted(self.errors)
-        if p in self.errors:
-            return self.errors[p]
+    def _table(self, L, theta) -> dict:
+        if self.errors is None:
+            raise RuntimeError("the tuner is not calibrated")
+        if (None, theta) in self.errors:
+            return self.errors[(None, theta)]
+        if (L, theta) in self.errors:
+            return self.errors[(L, theta)]
+        levs = sorted(l for (l, t) in self.errors if t == theta)
+        if not levs:
+            raise KeyError(f"theta {theta} is not calibrated")
+        above = [l for l in levs if L is not None and l >= L]
+        cand = above if above else [levs[-1]]
+        # the worst (largest) error of the candidate level counts, order by order
+        tabs = [self.errors[(l, theta)] for l in cand]
+        ps = sorted(set().union(*tabs))
+        return {p: max(t.get(p, 0.0) for t in tabs) for p in ps}
+
+    @staticmethod
+    def _geometric(tab: dict, p: int) -> float:
+        ps = sorted(tab)
+        if p in tab:
+            return tab[p]
         if len(ps) == 1:
-            return self.errors[ps[0]] if p > ps[0] else math.inf
-        # geometric inter- or extrapolation between the two nearest calibrated orders
+            return tab[ps[0]] if p > ps[0] else math.inf
         if p < ps[0]:
             a, b = ps[0], ps[1]
         elif p > ps[-1]:
@@ -136,53 +163,88 @@ class Tuner:
         else:
             b = next(q for q in ps if q > p)
             a = max(q for q in ps if q < p)
-        ea, eb = max(self.errors[a], 1e-300), max(self.errors[b], 1e-300)
-        rate = (eb / ea) ** (1.0 / (b - a))
-        return ea * rate ** (p - a)
+        ea, eb = max(tab[a], 1e-300), max(tab[b], 1e-300)
+        return ea * (eb / ea) ** ((p - a) / (b - a))
 
-    def model(self, p: int) -> float:
+    def model(self, p: int, L: int | None = None, theta: float | None = None) -> float:
         """Modelled worst error at order p: non-increasing in p."""
-        if self.errors is None:
-            raise RuntimeError("the tuner is not calibrated")
-        return max(self._raw(q) for q in range(p, self.pmax + 1))
+        tab = self._table(L, self.theta if theta is None else theta)
+        return max(self._geometric(tab, q) for q in range(p, self.pmax + 1))
 
-    def order(self, tol: float) -> int:
+    def order(self, tol: float, L: int | None = None, theta: float | None = None) -> int:
         for p in range(self.pmax + 1):
-            if self.kSafety * self.model(p) <= tol:
+            if self.kSafety * self.model(p, L, theta) <= tol:
                 return p
         return self.pmax
 
-    def choose(self, n: int, tol: float) -> tuple[int, float, int, int]:
-        p = self.order(tol)
-        prec = fmm.FMM_PREC_MIXED if (tol >= 1e-6 and p <= 15) else fmm.FMM_PREC_F64
-        return self.levels(n), self.theta, p, prec
+    def _cost(self, L, theta, prec, p) -> float:
+        c = None
+        for key in ((L, theta, prec), (None, theta, prec)):
+            if key in self.cost:
+                c = self.cost[key]
+                break
+        if not c:
+            return float(p + 1) ** 3  # no measurement: the work of the translations
+        if p in c:
+            return c[p]
+        q = max(c) if p > max(c) else min(c)
+        return c[q] * ((p + 1) / (q + 1)) ** 3
 
-    def calibrate(self, n: int = 20_000, orders=range(1, 17), seed: int = 7, stream=None) -> dict:
-        """Measure errors[p] on the GPU: relative error (normwise, potential
-        and field, the larger) of the FMM against the direct sum, the largest
-        over the served distributions."""
+    def choose(self, n: int, tol: float) -> tuple[int, float, int, int]:
+        L = self.levels(n)
+        thetas = sorted({t for (_, t) in self.errors}) if self.errors else [self.theta]
+        best = None
+        for th in thetas:
+            p = self.order(tol, L, th)
+            prec = fmm.FMM_PREC_MIXED if (tol >= self.kMixedMinTol and p <= 15) else fmm.FMM_PREC_F64
+            key = (self._cost(L, th, prec, p), p, th)
+            if best is None or key < best[0]:
+                best = (key, (L, th, p, prec))
+        return best[1]
+
+    def calibrate(self, levels=(2, 3, 4), thetas=(0.4, 0.5), orders=range(1, 17), seed: int = 7,
+                  stream=None) -> dict:
+        """Measure errors and costs on the GPU: for each level count L a cloud
+        of about kPointsPerLeaf * 8^L points of every served distribution, its
+        direct sum, and the FMM at every theta and order (binary64; mixed
+        precision timed as well up to order 10)."""
         import torch
         table = {}
-        worst: dict[int, float] = {}
-        for dist in DISTRIBUTIONS:
-            req = Request(-1, 0.0, dist, n, 0.0, seed)
-            x, y, z, q = request_points(req)
-            dev = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in (x, y, z, q)]
-            ref = direct_sum(*dev, stream)
-            lev = self.levels(n)
-            tree = fmm.fmm_build(*dev[:3], lev, self.theta, stream)
-            out = [torch.empty_like(dev[0]) for _ in range(4)]
-            for p in orders:
-                fmm.fmm_evaluate_tree(tree, dev[3], p, *out, stream)
-                torch.cuda.synchronize()
-                e_phi = float(torch.linalg.norm(out[0] - ref[0]) / torch.linalg.norm(ref[0]))
-                num = sum(float(torch.sum((a - b) ** 2)) for a, b in zip(out[1:], ref[1:]))
-                den = sum(float(torch.sum(b ** 2)) for b in ref[1:])
-                err = max(e_phi, math.sqrt(num / den))
-                table[(dist, p)] = err
-                worst[p] = max(worst.get(p, 0.0), err)
-            tree.free()
-        self.errors = worst
+        errs: dict = {}
+        cost: dict = {}
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for L in levels:
+            n = int(self.kPointsPerLeaf * 8 ** L)
+            for dist in DISTRIBUTIONS:
+                req = Request(-1, 0.0, dist, n, 0.0, seed)
+                x, y, z, q = request_points(req)
+                dev = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in (x, y, z, q)]
+                ref = direct_sum(*dev, stream)
+                out = [torch.empty_like(dev[0]) for _ in range(4)]
+                for th in thetas:
+                    tree = fmm.fmm_build(*dev[:3], L, th, stream)
+                    for p in orders:
+                        precs = [fmm.FMM_PREC_F64] + ([fmm.FMM_PREC_MIXED] if p <= 10 else [])
+                        for prec in precs:
+                            fmm.fmm_evaluate_tree(tree, dev[3], p, *out, stream, precision=prec)  # warm
+                            ev0.record()
+                            fmm.fmm_evaluate_tree(tree, dev[3], p, *out, stream, precision=prec)
+                            ev1.record()
+                            torch.cuda.synchronize()
+                            c = cost.setdefault((L, th, prec), {})
+                            c[p] = max(c.get(p, 0.0), ev0.elapsed_time(ev1) * 1e-3 / n)
+                            if prec != fmm.FMM_PREC_F64:
+                                continue
+                            e_phi = float(torch.linalg.norm(out[0] - ref[0]) / torch.linalg.norm(ref[0]))
+                            num = sum(float(torch.sum((a - b) ** 2)) for a, b in zip(out[1:], ref[1:]))
+                            den = sum(float(torch.sum(b ** 2)) for b in ref[1:])
+                            err = max(e_phi, math.sqrt(num / den))
+                            table[(L, dist, th, p)] = err
+                            e = errs.setdefault((L, th), {})
+                            e[p] = max(e.get(p, 0.0), err)
+                    tree.free()
+        self.errors = errs
+        self.cost = cost
         return table
 
 
@@ -265,8 +327,8 @@ class Server:
                 if item is None:
                     return
                 r, data = item
-                lev = self.tuner.levels(r.n)
-                est = int(fmm.fmm_bytes_estimate(r.n, lev, self.tuner.theta, self.tuner.order(r.tol)))
+                lev, th, p, _ = self.tuner.choose(r.n, r.tol)
+                est = int(fmm.fmm_bytes_estimate(r.n, lev, th, p))
                 self._admit(est)
                 start = time.perf_counter() - t0[0]
                 try:
@@ -328,8 +390,11 @@ def run_stream(nreq: int = 4000, rate: float = 200.0, workers: int = 6, check_ev
     out = summary(results, reqs)
     out.update({"workers": workers, "hbm_budget_gb": round(hbm_budget / 2 ** 30, 1),
                 "peak_concurrency": srv.peak_concurrency, "peak_bytes_gb": round(srv.peak_bytes / 1e9, 3),
-                "tuner_errors": {p: float(f"{e:.3g}") for p, e in sorted(tuner.errors.items())},
-                "orders": {str(t): tuner.order(t) for t in (1e-4, 1e-8)}, "calibration_s": round(cal_s, 2)})
+                "tuner_errors": {f"L{l} theta{t}": {p: float(f"{e:.3g}") for p, e in sorted(v.items())}
+                                 for (l, t), v in sorted(tuner.errors.items())},
+                "choices": {f"n={n} tol={t:g}": list(tuner.choose(n, t)) for n in (1000, 20_000, 200_000)
+                            for t in (1e-4, 1e-8)},
+                "calibration_s": round(cal_s, 2)})
     checks = []
     stream = torch.cuda.Stream()
     keep = Server(tuner, workers=1, keep_outputs=True)

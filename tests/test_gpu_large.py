@@ -1,0 +1,121 @@
+"""The 2^24-point Plummer workload (scale radius 0.05, 6 levels) at full
+size, checked through properties that hold at any size: every leaf holds the
+number of points that repeated floor(n/2) splits give, the permutation is
+complete, every point lies in its leaf's cell, and both precisions are within
+1e-6 of the direct sum (eq. (2.1)) at 10,000 sampled points.  The direct sum
+runs on the GPU as a theta = 0 evaluation at separate targets (all P2P, the
+path the parity tests check against the oracle)."""
+import numpy as np
+import pytest
+
+from paper_2002_04894_amd import workloads as W
+from test_gpu_parity import F, dev, say, torch  # noqa: F401 (fixtures)
+
+pytestmark = pytest.mark.gpu
+
+
+def median_counts(n: int, levels: int) -> np.ndarray:
+    """Leaf sizes of 3 * levels rounds of median bisection (low side floor(c/2))."""
+    c = np.array([n], dtype=np.int64)
+    for _ in range(3 * levels):
+        low = c // 2
+        c = np.stack([low, c - low], axis=1).reshape(-1)
+    return c
+
+
+def test_median_counts_closed_form():
+    assert list(median_counts(5, 1)) == [0, 1, 0, 1, 0, 1, 1, 1]
+    assert median_counts(1 << 24, 6).min() == median_counts(1 << 24, 6).max() == 64
+
+
+def direct_at(torch, F, X, Y, Z, Q, idx):
+    T = [a.index_select(0, idx).contiguous() for a in (X, Y, Z)]
+    tree = F.fmm_build_ex(X, Y, Z, 2, 0.0, targets=tuple(T))
+    d = [torch.empty(idx.numel(), dtype=torch.float64, device="cuda") for _ in range(4)]
+    F.fmm_evaluate_targets(tree, Q, 0, *d)
+    torch.cuda.synchronize()
+    tree.free()
+    return [a.cpu().numpy() for a in d]
+
+
+def rel(g, d):
+    ephi = np.linalg.norm(g[0] - d[0]) / np.linalg.norm(d[0])
+    eE = np.linalg.norm(np.concatenate(g[1:]) - np.concatenate(d[1:])) / np.linalg.norm(np.concatenate(d[1:]))
+    return ephi, eE
+
+
+def test_plummer16m_full_size(torch, F):
+    x, y, z, q, w = W.workload("plummer16m")
+    n, L, theta, p = x.shape[0], w["levels"], w["theta"], w["p"]
+    say(f"[large] plummer16m: n={n} L={L} theta={theta} p={p}")
+    X, Y, Z, Q = (dev(torch, a) for a in (x, y, z, q))
+    gt = F.fmm_build(X, Y, Z, L, theta)
+    perm = F.fmm_tree_perm(gt)
+    assert np.array_equal(np.sort(perm), np.arange(n, dtype=np.int32))
+    geom, start = F.fmm_tree_boxes(gt, L)
+    counts = np.diff(start)
+    assert np.array_equal(counts, median_counts(n, L))
+    leaf = np.repeat(np.arange(8 ** L), counts)
+    P = np.stack([x[perm], y[perm], z[perm]], axis=1)
+    assert np.all(P >= geom[leaf, 0:3]) and np.all(P <= geom[leaf, 3:6])
+    del P, leaf
+    say("[large] evaluate binary64 and mixed")
+    outs = {}
+    for prec in (F.FMM_PREC_F64, F.FMM_PREC_MIXED):
+        o = [torch.empty_like(X) for _ in range(4)]
+        F.fmm_evaluate_tree(gt, Q, p, *o, precision=prec)
+        torch.cuda.synchronize()
+        outs[prec] = o
+    gt.free()
+    tg = W.sample_targets(n, 10_000, seed=1)
+    idx = torch.from_numpy(tg).to("cuda")
+    say("[large] direct sum at 10,000 sampled points")
+    d = direct_at(torch, F, X, Y, Z, Q, idx)
+    for prec, o in outs.items():
+        g = [a.index_select(0, idx).cpu().numpy() for a in o]
+        ephi, eE = rel(g, d)
+        say(f"[large] precision {prec}: phi {ephi:.2e} E {eE:.2e}")
+        assert ephi <= 1e-6 and eE <= 1e-6
+    # mixed against binary64 over all points
+    a = [t.cpu().numpy() for t in outs[F.FMM_PREC_F64]]
+    b = [t.cpu().numpy() for t in outs[F.FMM_PREC_MIXED]]
+    dphi, dE = rel(b, a)
+    assert dphi <= 1e-6 and dE <= 1e-6
+
+
+def test_plummer16m_theta_p_grid(torch, F):
+    """The clustered-cloud grid: theta in {0.4, 0.5, 0.6} x p in {8, 12} in
+    both precisions (p 16 in binary64 at theta 0.5; mixed precision runs
+    binary64 above order 15).  Errors against the direct sum at 10,000
+    sampled points are printed; mixed stays within 1e-6 of binary64, the
+    error falls with p at fixed theta, and p 12 reaches 1e-6 at theta 0.5."""
+    x, y, z, q, w = W.workload("plummer16m")
+    n, L = x.shape[0], w["levels"]
+    X, Y, Z, Q = (dev(torch, a) for a in (x, y, z, q))
+    tg = W.sample_targets(n, 10_000, seed=1)
+    idx = torch.from_numpy(tg).to("cuda")
+    d = direct_at(torch, F, X, Y, Z, Q, idx)
+    o = [torch.empty_like(X) for _ in range(4)]
+
+    def run(gt, p, prec):
+        F.fmm_evaluate_tree(gt, Q, p, *o, precision=prec)
+        torch.cuda.synchronize()
+        return [a.index_select(0, idx).cpu().numpy() for a in o]
+
+    for theta in (0.4, 0.5, 0.6):
+        gt = F.fmm_build(X, Y, Z, L, theta)
+        errs = {}
+        for p in (8, 12) + ((16,) if theta == 0.5 else ()):
+            g64 = run(gt, p, F.FMM_PREC_F64)
+            errs[p] = max(rel(g64, d))
+            line = f"[grid] theta {theta} p {p}: binary64 {errs[p]:.2e}"
+            if p <= 15:
+                g32 = run(gt, p, F.FMM_PREC_MIXED)
+                line += f" mixed {max(rel(g32, d)):.2e} mixed-vs-f64 {max(rel(g32, g64)):.2e}"
+                assert max(rel(g32, g64)) <= 1e-6
+            say(line)
+        ps = sorted(errs)
+        assert all(errs[a] > errs[b] for a, b in zip(ps, ps[1:]))
+        if theta == 0.5:
+            assert errs[12] <= 1e-6
+        gt.free()

@@ -58,6 +58,33 @@ def test_tuner_rules():
         serve.Tuner().order(1e-4)
 
 
+def test_tuner_levels_theta_and_cost():
+    """Per level count and theta: a request uses the table of its own level
+    count (uncalibrated depths: the worst calibrated one at or above, else the
+    deepest), and among the thetas that meet the accuracy the cheapest by
+    measured cost wins."""
+    e3 = {p: 1e-3 * 0.5 ** p for p in range(1, 17)}
+    e4 = {p: 4e-3 * 0.5 ** p for p in range(1, 17)}           # deeper tree: 4x the error
+    e4s = {p: 4e-3 * 0.4 ** p for p in range(1, 17)}          # smaller theta converges faster
+    errors = {(3, 0.5): e3, (4, 0.5): e4, (4, 0.4): e4s, (3, 0.4): {p: 1e-3 * 0.4 ** p for p in range(1, 17)}}
+    cost = {(4, 0.5, 0): {p: 1.0 * (p + 1) ** 2 for p in range(1, 17)},
+            (4, 0.4, 0): {p: 1.3 * (p + 1) ** 2 for p in range(1, 17)}}
+    t = serve.Tuner(errors=errors, cost=cost)
+    L, th, p, prec = t.choose(150_000, 1e-8)
+    assert L == 4 and prec == 0
+    assert 2 * t.model(p, 4, th) <= 1e-8
+    # theta 0.5 needs p 20 (2 * 4e-3 * 0.5^20 = 7.6e-9), theta 0.4 needs p 15
+    # (8.6e-9); costs 1.3 * 16^2 = 333 against 17^2 * (21/17)^3 = 545 (p 20 lies
+    # beyond the measured orders), so theta 0.4 is chosen
+    assert (th, p) == (0.4, 15)
+    # the same accuracy at 3 levels: its own, smaller errors
+    assert t.order(1e-8, 3, 0.5) < t.order(1e-8, 4, 0.5)
+    # uncalibrated depths: deeper than calibrated -> the deepest table
+    assert t.model(10, 6, 0.5) == e4[10]
+    # shallower -> the worst calibrated table at or above it
+    assert t.model(10, 2, 0.5) == max(e3[10], e4[10])
+
+
 def test_tuner_model_is_monotone():
     """A measurement that rises with p (noise, or the rounding floor) must
     not let the tuner pick the lower order."""
