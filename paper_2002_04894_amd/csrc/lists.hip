@@ -13,12 +13,15 @@
 namespace fmm {
 namespace {
 
-__device__ __forceinline__ bool is_weak(const double* gi, const double* gj, double theta) {
+// eq. (2.2) for box i (geometry gi) and a candidate with centre (cjx, cjy,
+// cjz) and radius rj; evaluated as written, without FMA contraction
+__device__ __forceinline__ bool is_weak(const double* gi, double cjx, double cjy, double cjz, double rj,
+                                        double theta) {
 #pragma clang fp contract(off)
-  const double dx = gi[6] - gj[6], dy = gi[7] - gj[7], dz = gi[8] - gj[8];
+  const double dx = gi[6] - cjx, dy = gi[7] - cjy, dz = gi[8] - cjz;
   const double d = sqrt((dx * dx + dy * dy) + dz * dz);
   if (!(d > 0.0)) return false;
-  const double ri = gi[9], rj = gj[9];
+  const double ri = gi[9];
   const double R = ri > rj ? ri : rj;
   const double r = ri > rj ? rj : ri;
   return R + theta * r <= theta * d;
@@ -26,6 +29,10 @@ __device__ __forceinline__ bool is_weak(const double* gi, const double* gj, doub
 
 // One wave per target box i; lanes take 64 consecutive candidates at a time
 // and a ballot compacts them, so each row keeps ascending candidate order.
+// kListGroups groups of 64 candidates are in flight together: their index and
+// geometry loads are issued before any of them is tested.
+constexpr int kListGroups = 4;
+
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_lists(int64_t nbox, const double* __restrict__ geom,
                                                const int64_t* __restrict__ ps_off, const int32_t* __restrict__ ps_idx,
@@ -46,19 +53,32 @@ __global__ __launch_bounds__(256) void k_lists(int64_t nbox, const double* __res
     wo = w_off[i];
   }
   int64_t cs = 0, cw = 0;
-  for (int64_t k0 = 0; k0 < ncand; k0 += 64) {
-    const int64_t k = k0 + lane;
-    const bool valid = k < ncand;
-    const int64_t j = valid ? 8 * (int64_t)ps_idx[e0 + (k >> 3)] + (k & 7) : 0;
-    const bool weak = valid && (j != i) && is_weak(gi, geom + j * 10, theta);
-    const bool strong = valid && !weak;
-    const uint64_t mw = __ballot(weak), ms = __ballot(strong);
-    if (FILL) {
-      if (weak) w_idx[wo + cw + __popcll(mw & below)] = (int32_t)j;
-      if (strong) s_idx[so + cs + __popcll(ms & below)] = (int32_t)j;
+  for (int64_t k0 = 0; k0 < ncand; k0 += 64 * kListGroups) {
+    int64_t j[kListGroups];
+    bool valid[kListGroups];
+#pragma unroll
+    for (int u = 0; u < kListGroups; ++u) {
+      const int64_t k = k0 + 64 * u + lane;
+      valid[u] = k < ncand;
+      j[u] = valid[u] ? 8 * (int64_t)ps_idx[e0 + (k >> 3)] + (k & 7) : i;
     }
-    cw += __popcll(mw);
-    cs += __popcll(ms);
+    double c[kListGroups][4];
+#pragma unroll
+    for (int u = 0; u < kListGroups; ++u)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) c[u][a] = geom[j[u] * 10 + 6 + a];
+#pragma unroll
+    for (int u = 0; u < kListGroups; ++u) {
+      const bool weak = valid[u] && (j[u] != i) && is_weak(gi, c[u][0], c[u][1], c[u][2], c[u][3], theta);
+      const bool strong = valid[u] && !weak;
+      const uint64_t mw = __ballot(weak), ms = __ballot(strong);
+      if (FILL) {
+        if (weak) w_idx[wo + cw + __popcll(mw & below)] = (int32_t)j[u];
+        if (strong) s_idx[so + cs + __popcll(ms & below)] = (int32_t)j[u];
+      }
+      cw += __popcll(mw);
+      cs += __popcll(ms);
+    }
   }
   if (!FILL && lane == 0) {
     ns[i] = (int32_t)cs;
