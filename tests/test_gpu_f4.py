@@ -152,3 +152,28 @@ def test_f4_argument_checks(torch, F):
     assert gt.m == 0 and F.fmm_tree_targets(gt).shape == (0,)
     gpu_eval_targets(torch, F, gt, q, 3)
     gt.free()
+
+
+def test_targets_zero_levels_and_faces(torch, F, orc):
+    """Targets at L = 0 (all P2P), and targets placed exactly on the shared
+    faces, edges and corners of leaf cells, where several cells contain them:
+    the leaf chosen and the values match the oracle."""
+    x, y, z, q = W.gaussian_mixture(3000, seed=21)
+    # L = 0: one leaf, the direct sum at the targets
+    tx, ty, tz = targets_for(x, y, z, 200, seed=22)
+    ot = orc.Tree(x, y, z, 0, 0.5, targets=(tx, ty, tz))
+    gt = gpu_build(torch, F, x, y, z, 0, 0.5, 1.0, targets=(tx, ty, tz))
+    assert_close(gpu_eval_targets(torch, F, gt, q, 3), ot.evaluate_targets(q, 3), what="targets L=0")
+    gt.free()
+    # cell corners and face centres of the leaves of a 2-level tree (their
+    # geometry does not depend on the targets as long as they lie inside the
+    # sources' bounding box)
+    g = orc.Tree(x, y, z, 2, 0.5).geom(2)
+    pts = np.concatenate([g[:, 0:3], g[:, 3:6], np.c_[g[:, 0], g[:, 7], g[:, 8]], np.c_[g[:, 6], g[:, 4], g[:, 8]]])
+    tx, ty, tz = (np.ascontiguousarray(pts[:, k]) for k in range(3))
+    ot = orc.Tree(x, y, z, 2, 0.5, targets=(tx, ty, tz))
+    assert np.array_equal(ot.geom(2), g)
+    gt = gpu_build(torch, F, x, y, z, 2, 0.5, 1.0, targets=(tx, ty, tz))
+    assert np.array_equal(F.fmm_tree_targets(gt), [ot.locate(*v) for v in pts])
+    assert_close(gpu_eval_targets(torch, F, gt, q, 6), ot.evaluate_targets(q, 6), what="targets on faces")
+    gt.free()

@@ -276,6 +276,19 @@ def test_full_size_gmix1m_sampled(torch, F, orc):
     gt.free()
 
 
+@pytest.mark.parametrize("p,L", [(17, 2), (18, 2), (20, 2)])
+def test_parity_binary64_above_mfma_orders(torch, F, orc, p, L):
+    """Orders above 15 run M2L on the binary64 VALU kernel: with weak pairs,
+    M2M and L2L against the oracle."""
+    say(f"[valu] p={p} L={L}")
+    x, y, z, q = make("gmix", 3000, seed=p)
+    ot = orc.Tree(x, y, z, L, 0.5)
+    assert ot.lists(L, 1)[1].size > 0
+    gt = gpu_tree(torch, F, x, y, z, L, 0.5)
+    assert_close(gpu_eval(torch, F, gt, q, p), ot.evaluate(q, p), what=f"p={p} L={L}")
+    gt.free()
+
+
 @pytest.mark.parametrize("n,L", [(8192, 2), (8300, 3), (12000, 2), (16383, 2)])
 def test_parity_sizes_with_one_chunked_round(torch, F, orc, n, L):
     """8192 <= n < 16384 source points: only the first bisection round (one
