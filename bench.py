@@ -87,6 +87,8 @@ def main():
                     help="steps of the mixed-precision mode timed after the binary64 ones (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the served-stream leg run after the timed steps (0: skip)")
+    ap.add_argument("--tuned-steps", type=int, default=5,
+                    help="steps of the autotuned legs at 1e-6 (mixed allowed, and binary64 only; 0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run one plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -189,24 +191,63 @@ def main():
         mouts = [torch.empty_like(X) for _ in range(4)]
         line["mixed"] = mixed_leg(step, mouts, outs, n, args.mixed_steps, stream, torch)
 
-    if n > ORACLE_GATE_MAX_N:
-        # the oracle's single-core direct sum is too slow here: the direct sum
-        # at sampled targets runs on the GPU instead (see gpu_direct_gate)
-        line["accuracy"] = gpu_direct_gate(X, Y, Z, Q, outs, torch)
-        if mouts is not None:
-            line["mixed"]["accuracy"] = gpu_direct_gate(X, Y, Z, Q, mouts, torch)
+    line["accuracy"] = gpu_direct_gate(X, Y, Z, Q, outs, torch)
+    if mouts is not None:
+        line["mixed"]["accuracy"] = gpu_direct_gate(X, Y, Z, Q, mouts, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w)
-        if n <= ORACLE_GATE_MAX_N:
-            line["accuracy"] = accuracy_gate(x, y, z, q, outs)
-            if mouts is not None:
-                line["mixed"]["accuracy"] = accuracy_gate(x, y, z, q, mouts)
+    if args.tuned_steps > 0 and n <= TUNED_MAX_N:
+        line["tuned"] = tuned_legs(X, Y, Z, Q, L, args.tuned_steps, stream, torch)
     if args.serve_requests > 0:
         line["serving"] = serving_leg(args.serve_requests)
     print(json.dumps(line), flush=True)
 
 
-ORACLE_GATE_MAX_N = 1 << 22
+TUNED_MAX_N = 1 << 22  # the tuned legs calibrate on clouds of the workload's size
+
+
+def tuned_legs(X, Y, Z, Q, L, steps, stream, torch, tol: float = 1e-6) -> dict:
+    """The workload at the metric's accuracy with theta, p and precision
+    picked by the autotuner (serve.Tuner, calibrated on the GPU at this level
+    count): its choice with mixed precision allowed, and the same with
+    binary64 forced (then p is the smallest binary64 order that meets tol at
+    the chosen theta).  Each: ms per step (build + evaluate) and the error
+    against the direct sum at 10,000 sampled points (gpu_direct_gate)."""
+    from paper_2002_04894_amd import serve
+    n = X.numel()
+    tuner = serve.Tuner()
+    t0 = time.perf_counter()
+    tuner.calibrate(levels=(L,), orders=range(1, 14))
+    cal_s = time.perf_counter() - t0
+    out = {"tol": tol, "calibration_s": round(cal_s, 2)}
+    lev, th, p, prec = tuner.choose(n, tol)
+    legs = {"mixed_allowed": (lev, th, p, prec), "f64": (lev, th, tuner.order(tol, lev, th), fmm.FMM_PREC_F64)}
+    for name, (lv, t_, p_, pr) in legs.items():
+        o = [torch.empty_like(X) for _ in range(4)]
+
+        def step():
+            tr = fmm.fmm_build(X, Y, Z, lv, t_, stream)
+            fmm.fmm_evaluate_tree(tr, Q, p_, *o, stream, precision=pr)
+            return tr
+
+        step().free()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        last = None
+        for _ in range(steps):
+            tr = step()
+            if last is not None:
+                last.free()
+            last = tr
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        last.free()
+        ms = ev0.elapsed_time(ev1) / steps
+        out[name] = {"levels": lv, "theta": t_, "p": p_, "precision": "mixed" if pr else "f64",
+                     "ms_per_step": round(ms, 4), "value": round(n / (ms * 1e-3), 1), "unit": "points/s",
+                     "accuracy": gpu_direct_gate(X, Y, Z, Q, o, torch)}
+    return out
 
 
 def serving_leg(nreq: int) -> dict:
@@ -229,7 +270,8 @@ def gpu_direct_gate(X, Y, Z, Q, outs, torch, k: int = 10_000) -> dict:
     computed on the GPU: a 2-level tree with theta = 0 makes every pair of
     leaves strongly connected, so the evaluation at the sampled points, given
     as separate targets, is the plain pairwise sum (no expansions; a target's
-    own source is skipped).  That path is the P2P of the parity tests."""
+    own source is skipped).  That path is the P2P that the parity tests check
+    against the oracle."""
     n = X.numel()
     tg = workloads.sample_targets(n, k, seed=1)
     idx = torch.from_numpy(tg).to("cuda")
@@ -307,18 +349,6 @@ def cpu_baseline(w):
             "seconds": round(dt, 2),
             "sample": f"gmix generator, n={ns}, levels={Ls}, theta={w['theta']}, p={w['p']}; full tree + upward "
                       f"pass, evaluation at the {pts} points of {len(leaves)} of {8 ** Ls} leaves"}
-
-
-def accuracy_gate(x, y, z, q, outs):
-    """Relative error of the GPU result vs the direct sum (eq. 2.1, computed
-    by the oracle) on 1,000 sampled targets."""
-    import oracle
-    tg = workloads.sample_targets(x.shape[0], 1000, seed=1)
-    d = oracle.direct(x, y, z, q, targets=tg)
-    g = [o.cpu().numpy()[tg] for o in outs]
-    ephi = float(np.linalg.norm(g[0] - d[0]) / np.linalg.norm(d[0]))
-    eE = float(np.linalg.norm(np.concatenate(g[1:]) - np.concatenate(d[1:])) / np.linalg.norm(np.concatenate(d[1:])))
-    return {"targets": 1000, "rel_err_phi": ephi, "rel_err_E": eE, "ok": bool(ephi <= 1e-6 and eE <= 1e-6)}
 
 
 if __name__ == "__main__":
