@@ -19,9 +19,13 @@ __all__ = [
     "gaussian_mixture",
     "plummer",
     "sphere_surface",
+    "spherical_gaussian",
+    "spherical_shell",
+    "helix",
     "workload",
     "WORKLOADS",
     "sample_targets",
+    "RESPONSE_DISTRIBUTIONS",
 ]
 
 
@@ -85,6 +89,57 @@ def sphere_surface(n: int, seed: int = 0, charges: str = "pm1"):
     q = _charges(rng, n, charges)
     return (np.ascontiguousarray(d[:, 0]), np.ascontiguousarray(d[:, 1]),
             np.ascontiguousarray(d[:, 2]), q)
+
+
+def spherical_gaussian(n: int, seed: int = 0, sigma: float = 1.0, charges: str = "pm1"):
+    """One isotropic Gaussian about the origin, standard deviation `sigma`
+    per axis (the spherical Gaussian of Section 3.2)."""
+    rng = np.random.default_rng(seed)
+    pts = sigma * rng.standard_normal((n, 3))
+    q = _charges(rng, n, charges)
+    return (np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1]),
+            np.ascontiguousarray(pts[:, 2]), q)
+
+
+def spherical_shell(n: int, seed: int = 0, r_in: float = 0.9, r_out: float = 1.0,
+                    charges: str = "pm1"):
+    """Points uniform in the volume between radii r_in and r_out (the
+    spherical shell of Section 3.2): radius by inverse CDF, r^3 uniform
+    between r_in^3 and r_out^3, then an isotropic direction."""
+    rng = np.random.default_rng(seed)
+    u = rng.random(n)
+    r = np.cbrt(r_in ** 3 + u * (r_out ** 3 - r_in ** 3))
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pts = d * r[:, None]
+    q = _charges(rng, n, charges)
+    return (np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1]),
+            np.ascontiguousarray(pts[:, 2]), q)
+
+
+def helix(n: int, seed: int = 0, turns: float = 5.0, radius: float = 1.0, height: float = 2.0,
+          jitter: float = 0.02, charges: str = "pm1"):
+    """Points along a circular helix about the z axis (the helix of Section
+    3.2): parameter t uniform in [0, 1), angle 2*pi*turns*t, z from
+    -height/2 to height/2, then an isotropic Gaussian offset of standard
+    deviation `jitter` per axis."""
+    rng = np.random.default_rng(seed)
+    t = rng.random(n)
+    a = 2.0 * np.pi * turns * t
+    pts = np.stack([radius * np.cos(a), radius * np.sin(a), height * (t - 0.5)], axis=1)
+    pts += jitter * rng.standard_normal((n, 3))
+    q = _charges(rng, n, charges)
+    return (np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1]),
+            np.ascontiguousarray(pts[:, 2]), q)
+
+
+# The four distributions of the parameter-response study (Section 3.2).
+RESPONSE_DISTRIBUTIONS = {
+    "cube": uniform_cube,
+    "gaussian": spherical_gaussian,
+    "shell": spherical_shell,
+    "helix": helix,
+}
 
 
 # Named workloads: sizes, parameters and generator of each benchmarked case.
