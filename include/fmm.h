@@ -131,7 +131,10 @@ int fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int 
  * The root cell is the bounding box of the sources and the targets.  Each
  * target belongs to the leaf reached from the root by taking, at every
  * level, the first child (in child order) whose closed cell holds it.
- * Synchronises `stream` as fmm_build does, plus once for the targets.
+ * Synchronises `stream` as fmm_build does, plus once for the targets; for
+ * eta < 1 also once per bisection round, from the second, while every
+ * segment of the round before held at least 8192 points and the round has
+ * at most 512 segments (the segment sizes choose the round's kernels).
  */
 int fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, const double* tx, const double* ty,
                  const double* tz, int64_t m, int levels, double theta, double eta, void* stream, fmm_tree** out);

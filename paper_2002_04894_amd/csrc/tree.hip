@@ -16,6 +16,9 @@
 // Child cells are the parent cell cut at the plane; the child number is
 // 4*b1 + 2*b2 + b3 with b = 1 for the high side, so the segment index at
 // depth 3l is the box index at level l.
+#include <algorithm>
+#include <vector>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -835,17 +838,23 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, cons
   int2* cbase = nullptr;
   double2* cpart = nullptr;
   // the chunked rounds' state, allocated under the condition that selects
-  // them below: a round is chunked when every segment holds at least
-  // kMultiMin points, the first one (a single segment) when n >= kMultiMin
-  const bool any_multi = !blend && n >= kMultiMin;
+  // them below: a round is chunked when it has at most kMultiMaxSeg segments,
+  // every one holds at least kMultiMin points and the chunks fit in nblk_cap
+  // (the first round, a single segment, whenever n >= kMultiMin).  With
+  // eta = 1 the segment sizes follow from n; with eta < 1 children may be
+  // unequal, so each round's sizes are read back until a segment is smaller
+  // than kMultiMin (its children are no larger, so no later round qualifies).
+  const bool any_multi = n >= kMultiMin;
+  const int64_t nblk_cap = 2 * ((n + kChunk - 1) / kChunk + kMultiMaxSeg);
   if (any_multi) {
-    const int64_t nblk = (n + kChunk - 1) / kChunk + kMultiMaxSeg;  // chunks of any multi-block round
     sel = (SegSel*)dalloc(kMultiMaxSeg * sizeof(SegSel), s);
     ghist = (unsigned*)dalloc(kMultiMaxSeg * 256 * sizeof(unsigned), s);
-    ccount = (int2*)dalloc(nblk * sizeof(int2), s);
-    cbase = (int2*)dalloc(nblk * sizeof(int2), s);
-    cpart = (double2*)dalloc(nblk * sizeof(double2), s);
+    ccount = (int2*)dalloc(nblk_cap * sizeof(int2), s);
+    cbase = (int2*)dalloc(nblk_cap * sizeof(int2), s);
+    cpart = (double2*)dalloc(nblk_cap * sizeof(double2), s);
   }
+  std::vector<int32_t> hseg_n;
+  bool sizes_ok = true;  // eta < 1: no earlier round had a segment below kMultiMin
 
   int cur = 0;
   for (int depth = 0; depth < 3 * L; ++depth) {
@@ -853,8 +862,24 @@ void tree_build(Tree& t, const double* x, const double* y, const double* z, cons
     const int64_t maxn = (n + nsegd - 1) / nsegd;
     const int64_t minn = n / nsegd;
     const int o = cur ^ 1;
-    if (any_multi && minn >= kMultiMin && nsegd <= kMultiMaxSeg) {
-      const int nchunk = (int)((maxn + kChunk - 1) / kChunk);
+    bool multi = false;
+    int64_t seg_max = maxn;
+    if (any_multi && nsegd <= kMultiMaxSeg) {
+      if (!blend || depth == 0) {
+        multi = minn >= kMultiMin;
+      } else if (sizes_ok) {
+        hseg_n.resize((size_t)nsegd);
+        HIPCHECK(hipMemcpyAsync(hseg_n.data(), seg_n + (nsegd - 1), nsegd * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                s));
+        HIPCHECK(hipStreamSynchronize(s));
+        const auto mm = std::minmax_element(hseg_n.begin(), hseg_n.end());
+        sizes_ok = *mm.first >= kMultiMin;
+        seg_max = *mm.second;
+        multi = sizes_ok && nsegd * ((seg_max + kChunk - 1) / kChunk) <= nblk_cap;
+      }
+    }
+    if (multi) {
+      const int nchunk = (int)((seg_max + kChunk - 1) / kChunk);
       const unsigned nseg = (unsigned)nsegd, nblk = (unsigned)(nsegd * nchunk);
       k_mb_init<<<nseg, 256, 0, s>>>(cells, seg_n, depth, sel, ghist);
       HIPCHECK(hipGetLastError());

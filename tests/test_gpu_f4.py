@@ -65,9 +65,10 @@ def test_eta_tree_and_evaluation(torch, F, orc, gen, n, L, theta, eta, p):
     gt.free()
 
 
-def test_eta_large_single_block_rounds(torch, F, orc):
-    """eta < 1 runs every bisection round one block per segment, also the
-    first rounds over 2^18 points: tree bit for bit, values on sampled leaves."""
+def test_eta_large_chunked_rounds(torch, F, orc):
+    """eta < 1 over 2^18 points: the first rounds run chunked on segments of
+    unequal size (read back per round), the later ones one block per
+    segment: tree bit for bit, values on sampled leaves."""
     x, y, z, q = W.gaussian_mixture(1 << 18, seed=3)
     L, theta, eta, p = 4, 0.5, 0.5, 8
     say(f"[eta] gmix 2^18 L={L} eta={eta}")
@@ -80,6 +81,26 @@ def test_eta_large_single_block_rounds(torch, F, orc):
     s = ot.start(L)
     pts = np.concatenate([ot.perm()[s[b]:s[b + 1]] for b in leaves])
     assert_close([g[pts] for g in got], [r[pts] for r in ref], what="eta 0.5 sampled leaves")
+    gt.free()
+
+
+CHUNKED_ETA_CASES = [
+    # generator, n, levels, eta: unequal segments of at least 8192 points in
+    # the first rounds (chunked), then one block per segment
+    ("gaussian_mixture", 60_000, 2, 0.3),
+    ("spherical_gaussian", 100_000, 2, 0.0),
+    ("helix", 50_000, 2, 0.8),
+    ("uniform_cube", 70_000, 2, 0.5),
+]
+
+
+@pytest.mark.parametrize("gen,n,L,eta", CHUNKED_ETA_CASES, ids=[f"{c[0]}{c[1]}_eta{c[3]}" for c in CHUNKED_ETA_CASES])
+def test_eta_chunked_rounds_unequal_segments(torch, F, orc, gen, n, L, eta):
+    say(f"[eta] chunked {gen} n={n} L={L} eta={eta}")
+    x, y, z, q = getattr(W, gen)(n, seed=9)
+    ot = orc.Tree(x, y, z, L, 0.5, eta=eta)
+    gt = gpu_build(torch, F, x, y, z, L, 0.5, eta)
+    assert_tree_equal(F, gt, ot, L)
     gt.free()
 
 
