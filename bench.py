@@ -147,9 +147,12 @@ def main():
     m2l_ms = phase_avg["m2l"]
     m2l_flops = m2l_pairs * m2l_flops_per_pair(p)
     achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0
+    # orders up to 15 run the matrix-core kernel (binary64 MFMA, whose peak is
+    # the binary64 vector peak on this part); higher orders the vector kernel
+    mfma_path = p <= 15
     roofline = {
-        "kernel": "k_m2l",
-        "bound": "alu",
+        "kernel": f"k_m2l_mfma<{p}, double>" if mfma_path else "k_m2l",
+        "bound": "mfma" if mfma_path else "alu",
         "achieved": round(achieved, 3),
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
