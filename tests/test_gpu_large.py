@@ -4,12 +4,17 @@ number of points that repeated floor(n/2) splits give, the permutation is
 complete, every point lies in its leaf's cell, and both precisions are within
 1e-6 of the direct sum (eq. (2.1)) at 10,000 sampled points.  The direct sum
 runs on the GPU as a theta = 0 evaluation at separate targets (all P2P, the
-path the parity tests check against the oracle)."""
+path the parity tests check against the oracle).  Over theta x p, the values
+on sampled leaves are also compared with the oracle's, stored by a script
+that runs the oracle alone."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_2002_04894_amd import workloads as W
-from test_gpu_parity import F, dev, say, torch  # noqa: F401 (fixtures)
+from test_gpu_parity import F, assert_close, dev, say, torch  # noqa: F401 (fixtures)
 
 pytestmark = pytest.mark.gpu
 
@@ -83,12 +88,16 @@ def test_plummer16m_full_size(torch, F):
     assert dphi <= 1e-6 and dE <= 1e-6
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer16m_grid.json")
+
+
 def test_plummer16m_theta_p_grid(torch, F):
-    """The clustered-cloud grid: theta in {0.4, 0.5, 0.6} x p in {8, 12} in
-    both precisions (p 16 in binary64 at theta 0.5; mixed precision runs
-    binary64 above order 15).  Errors against the direct sum at 10,000
-    sampled points are printed; mixed stays within 1e-6 of binary64, the
-    error falls with p at fixed theta, and p 12 reaches 1e-6 at theta 0.5."""
+    """The clustered-cloud grid: theta in {0.4, 0.5, 0.6} x p in {8, 12, 16},
+    binary64 and (p <= 15) mixed precision.  Against the oracle's values on
+    sampled leaves (tests/golden/plummer16m_grid.json, written by the oracle
+    alone): binary64 within FP64_TOL, mixed within 1e-6.  Errors against the
+    direct sum at 10,000 sampled points are printed; the error falls with p
+    at fixed theta, and p 12 reaches 1e-6 at theta 0.5."""
     x, y, z, q, w = W.workload("plummer16m")
     n, L = x.shape[0], w["levels"]
     X, Y, Z, Q = (dev(torch, a) for a in (x, y, z, q))
@@ -96,6 +105,8 @@ def test_plummer16m_theta_p_grid(torch, F):
     idx = torch.from_numpy(tg).to("cuda")
     d = direct_at(torch, F, X, Y, Z, Q, idx)
     o = [torch.empty_like(X) for _ in range(4)]
+    with open(GOLDEN) as f:
+        golden = {row["theta"]: row for row in json.load(f)["grid"]}
 
     def run(gt, p, prec):
         F.fmm_evaluate_tree(gt, Q, p, *o, precision=prec)
@@ -104,13 +115,20 @@ def test_plummer16m_theta_p_grid(torch, F):
 
     for theta in (0.4, 0.5, 0.6):
         gt = F.fmm_build(X, Y, Z, L, theta)
+        gold = golden[theta]
+        gidx = torch.tensor(gold["index"], dtype=torch.int64, device="cuda")
         errs = {}
-        for p in (8, 12) + ((16,) if theta == 0.5 else ()):
+        for p in (8, 12, 16):
             g64 = run(gt, p, F.FMM_PREC_F64)
+            ref = [np.array(gold["orders"][str(p)][k]) for k in ("phi", "ex", "ey", "ez")]
+            at = [a.index_select(0, gidx).cpu().numpy() for a in o]
+            assert_close(at, ref, what=f"plummer16m theta {theta} p {p} vs oracle")
             errs[p] = max(rel(g64, d))
             line = f"[grid] theta {theta} p {p}: binary64 {errs[p]:.2e}"
             if p <= 15:
                 g32 = run(gt, p, F.FMM_PREC_MIXED)
+                at32 = [a.index_select(0, gidx).cpu().numpy() for a in o]
+                assert_close(at32, ref, tol=1e-6, what=f"plummer16m theta {theta} p {p} mixed vs oracle")
                 line += f" mixed {max(rel(g32, d)):.2e} mixed-vs-f64 {max(rel(g32, g64)):.2e}"
                 assert max(rel(g32, g64)) <= 1e-6
             say(line)
