@@ -46,6 +46,7 @@
 #include <complex.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -55,6 +56,25 @@
 #define IDX(n, m) ((n) * (n) + (n) + (m))
 
 typedef double complex cplx;
+
+/* Allocation that stops the process with a message when memory runs out
+ * (the lists of very large trees can exceed the host's memory). */
+static void* xmalloc(size_t bytes) {
+  void* p = malloc(bytes);
+  if (!p) {
+    fprintf(stderr, "oracle: out of host memory allocating %zu bytes\n", bytes);
+    abort();
+  }
+  return p;
+}
+static void* xcalloc(size_t count, size_t size) {
+  void* p = calloc(count, size);
+  if (!p) {
+    fprintf(stderr, "oracle: out of host memory allocating %zu x %zu bytes\n", count, size);
+    abort();
+  }
+  return p;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Direct sum, eq. (2.1).                                                   */
@@ -476,14 +496,14 @@ static int64_t bisect_median(const orc_tree* t, int32_t* perm, int64_t s, int64_
 static void build_tree(orc_tree* t) {
   const int L = t->L;
   const int64_t n = t->n;
-  t->perm = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  t->perm = (int32_t*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
   for (int64_t i = 0; i < n; ++i) t->perm[i] = (int32_t)i;
-  t->lev = (orc_level*)calloc((size_t)L + 1, sizeof(orc_level));
+  t->lev = (orc_level*)xcalloc((size_t)L + 1, sizeof(orc_level));
   int64_t nb = 1;
   for (int l = 0; l <= L; ++l, nb *= 8) {
     t->lev[l].nbox = nb;
-    t->lev[l].geom = (double*)calloc((size_t)nb * 10, sizeof(double));
-    t->lev[l].start = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
+    t->lev[l].geom = (double*)xcalloc((size_t)nb * 10, sizeof(double));
+    t->lev[l].start = (int64_t*)xcalloc((size_t)nb + 1, sizeof(int64_t));
   }
   /* root: tight bounding box of the sources and of the separate targets */
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -506,9 +526,9 @@ static void build_tree(orc_tree* t) {
   t->lev[0].start[0] = 0;
   t->lev[0].start[1] = n;
 
-  kv_t* kv = (kv_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(kv_t));
-  int32_t* tmp = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-  int32_t* scratch = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  kv_t* kv = (kv_t*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(kv_t));
+  int32_t* tmp = (int32_t*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t* scratch = (int32_t*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
   for (int l = 0; l < L; ++l) {
     orc_level* P = &t->lev[l];
     orc_level* C = &t->lev[l + 1];
@@ -586,10 +606,10 @@ static int is_weak(const double* gi, const double* gj, double theta) {
  * the parent of i, in ascending order. */
 static void build_lists(orc_tree* t) {
   orc_level* V0 = &t->lev[0];
-  V0->s_off = (int64_t*)malloc(2 * sizeof(int64_t));
-  V0->s_idx = (int32_t*)malloc(sizeof(int32_t));
-  V0->w_off = (int64_t*)calloc(2, sizeof(int64_t));
-  V0->w_idx = (int32_t*)malloc(sizeof(int32_t));
+  V0->s_off = (int64_t*)xmalloc(2 * sizeof(int64_t));
+  V0->s_idx = (int32_t*)xmalloc(sizeof(int32_t));
+  V0->w_off = (int64_t*)xcalloc(2, sizeof(int64_t));
+  V0->w_idx = (int32_t*)xmalloc(sizeof(int32_t));
   V0->s_off[0] = 0;
   V0->s_off[1] = 1;
   V0->s_idx[0] = 0;
@@ -597,10 +617,10 @@ static void build_lists(orc_tree* t) {
     orc_level* P = &t->lev[l - 1];
     orc_level* V = &t->lev[l];
     int64_t cap = 8 * P->s_off[P->nbox] * 8 + 1;
-    V->s_off = (int64_t*)malloc((size_t)(V->nbox + 1) * sizeof(int64_t));
-    V->w_off = (int64_t*)malloc((size_t)(V->nbox + 1) * sizeof(int64_t));
-    V->s_idx = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
-    V->w_idx = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+    V->s_off = (int64_t*)xmalloc((size_t)(V->nbox + 1) * sizeof(int64_t));
+    V->w_off = (int64_t*)xmalloc((size_t)(V->nbox + 1) * sizeof(int64_t));
+    V->s_idx = (int32_t*)xmalloc((size_t)cap * sizeof(int32_t));
+    V->w_idx = (int32_t*)xmalloc((size_t)cap * sizeof(int32_t));
     int64_t ns = 0, nw = 0;
     for (int64_t i = 0; i < V->nbox; ++i) {
       V->s_off[i] = ns;
@@ -628,7 +648,7 @@ static void build_lists(orc_tree* t) {
  * root cell so that every target lies in some leaf cell.  eta as in bisect. */
 void* orc_create_ex(int64_t n, const double* x, const double* y, const double* z, int64_t m, const double* tx,
                     const double* ty, const double* tz, int L, double theta, double eta) {
-  orc_tree* t = (orc_tree*)calloc(1, sizeof(orc_tree));
+  orc_tree* t = (orc_tree*)xcalloc(1, sizeof(orc_tree));
   t->n = n;
   t->L = L;
   t->theta = theta;
@@ -711,20 +731,20 @@ static cplx** far_pass(const orc_tree* t, const double* px, const double* py, co
   const int L = t->L;
   const int nt = NTERMS(p);
   const orc_level* leaf = &t->lev[L];
-  char** need = (char**)calloc((size_t)L + 1, sizeof(char*));
-  for (int l = 0; l <= L; ++l) need[l] = (char*)calloc((size_t)t->lev[l].nbox, 1);
+  char** need = (char**)xcalloc((size_t)L + 1, sizeof(char*));
+  for (int l = 0; l <= L; ++l) need[l] = (char*)xcalloc((size_t)t->lev[l].nbox, 1);
   for (int64_t s = 0; s < leaf->nbox; ++s) {
     if (!need_leaf[s]) continue;
     int64_t b = s;
     for (int l = L; l >= 0; --l, b /= 8) need[l][b] = 1;
   }
 
-  cplx** Mx = (cplx**)calloc((size_t)L + 1, sizeof(cplx*));
-  cplx** Lx = (cplx**)calloc((size_t)L + 1, sizeof(cplx*));
+  cplx** Mx = (cplx**)xcalloc((size_t)L + 1, sizeof(cplx*));
+  cplx** Lx = (cplx**)xcalloc((size_t)L + 1, sizeof(cplx*));
   {
     for (int l = 1; l <= L; ++l) {
-      Mx[l] = (cplx*)calloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
-      Lx[l] = (cplx*)calloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
+      Mx[l] = (cplx*)xcalloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
+      Lx[l] = (cplx*)xcalloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
     }
     /* P2M on level L */
     for (int64_t b = 0; b < leaf->nbox; ++b) {
@@ -792,17 +812,17 @@ int orc_evaluate(void* h, const double* q, int p, int parts, int64_t nleaves, co
 
   /* point data in tree order */
   const int64_t n = t->n;
-  double* px = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* py = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* pz = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* pq = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* px = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* py = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pz = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pq = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
   for (int64_t i = 0; i < n; ++i) {
     const int32_t o = t->perm[i];
     px[i] = t->x[o]; py[i] = t->y[o]; pz[i] = t->z[o]; pq[i] = q[o];
   }
 
   /* which boxes need a local expansion: ancestors of the listed leaves */
-  char* need_leaf = (char*)calloc((size_t)leaf->nbox, 1);
+  char* need_leaf = (char*)xcalloc((size_t)leaf->nbox, 1);
   for (int64_t s = 0; s < nleaves; ++s) need_leaf[leaves ? leaves[s] : s] = 1;
   cplx** Lx = ((parts & 2) && L >= 1) ? far_pass(t, px, py, pz, pq, p, need_leaf) : NULL;
   free(need_leaf);
@@ -891,20 +911,20 @@ int orc_evaluate_targets(void* h, const double* q, int p, int parts, double* phi
   const int nt = NTERMS(p);
   const orc_level* leaf = &t->lev[L];
   const int64_t n = t->n, m = t->m;
-  int64_t* tleaf = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+  int64_t* tleaf = (int64_t*)xmalloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
   for (int64_t k = 0; k < m; ++k) {
     tleaf[k] = orc_locate(h, t->tx[k], t->ty[k], t->tz[k]);
     if (tleaf[k] < 0) { free(tleaf); return -2; }
   }
-  double* px = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* py = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* pz = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double* pq = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* px = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* py = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pz = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  double* pq = (double*)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
   for (int64_t i = 0; i < n; ++i) {
     const int32_t o = t->perm[i];
     px[i] = t->x[o]; py[i] = t->y[o]; pz[i] = t->z[o]; pq[i] = q[o];
   }
-  char* need_leaf = (char*)calloc((size_t)leaf->nbox, 1);
+  char* need_leaf = (char*)xcalloc((size_t)leaf->nbox, 1);
   for (int64_t k = 0; k < m; ++k) need_leaf[tleaf[k]] = 1;
   cplx** Lx = ((parts & 2) && L >= 1) ? far_pass(t, px, py, pz, pq, p, need_leaf) : NULL;
   free(need_leaf);
