@@ -8,13 +8,14 @@ path the parity tests check against the oracle).  Over theta x p, the values
 on sampled leaves are also compared with the oracle's, stored by a script
 that runs the oracle alone."""
 import json
+import math
 import os
 
 import numpy as np
 import pytest
 
 from paper_2002_04894_amd import workloads as W
-from test_gpu_parity import F, assert_close, dev, say, torch  # noqa: F401 (fixtures)
+from test_gpu_parity import FP64_TOL, F, assert_close, dev, say, torch  # noqa: F401 (fixtures)
 
 pytestmark = pytest.mark.gpu
 
@@ -137,3 +138,47 @@ def test_plummer16m_theta_p_grid(torch, F):
         if theta == 0.5:
             assert errs[12] <= 1e-6
         gt.free()
+
+
+def test_plummer134m_full_size(torch, F):
+    """The 2^27-point Plummer workload (scale radius 0.02, charges in [-1, 1],
+    7 levels) at full size, theta 0.5, p 12, through properties that hold at
+    any size: leaf counts against the closed form, a complete permutation,
+    both precisions within 1e-6 of the direct sum at 10,000 sampled points,
+    and mixed precision within 1e-6 of binary64 over all points.  (The
+    oracle's lists alone would take about 90 GB of host memory at this size.)"""
+    x, y, z, q, w = W.workload("plummer134m")
+    n, L, theta, p = x.shape[0], w["levels"], w["theta"], w["p"]
+    say(f"[large] plummer134m: n={n} L={L} theta={theta} p={p}")
+    X, Y, Z, Q = (dev(torch, a) for a in (x, y, z, q))
+    del x, y, z, q
+    gt = F.fmm_build(X, Y, Z, L, theta)
+    perm = F.fmm_tree_perm(gt)
+    assert np.all(np.bincount(perm, minlength=n) == 1)
+    del perm
+    _, start = F.fmm_tree_boxes(gt, L)
+    assert np.array_equal(np.diff(start), median_counts(n, L))
+    tg = W.sample_targets(n, 10_000, seed=1)
+    idx = torch.from_numpy(tg).to("cuda")
+    outs = {}
+    for prec in (F.FMM_PREC_F64, F.FMM_PREC_MIXED):
+        say(f"[large] plummer134m: evaluate precision {prec}")
+        o = [torch.empty_like(X) for _ in range(4)]
+        F.fmm_evaluate_tree(gt, Q, p, *o, precision=prec)
+        torch.cuda.synchronize()
+        outs[prec] = o
+    gt.free()
+    a, b = outs[F.FMM_PREC_F64], outs[F.FMM_PREC_MIXED]
+    dphi = float(torch.linalg.norm(b[0] - a[0]) / torch.linalg.norm(a[0]))
+    dE = math.sqrt(sum(float(torch.sum((u - v) ** 2)) for u, v in zip(b[1:], a[1:])) /
+                   sum(float(torch.sum(v ** 2)) for v in a[1:]))
+    say(f"[large] plummer134m mixed vs binary64: phi {dphi:.2e} E {dE:.2e}")
+    assert dphi <= 1e-6 and dE <= 1e-6
+    got = {prec: [t.index_select(0, idx).cpu().numpy() for t in o] for prec, o in outs.items()}
+    del outs, a, b
+    say("[large] plummer134m: direct sum at 10,000 sampled points")
+    d = direct_at(torch, F, X, Y, Z, Q, idx)
+    for prec, g in got.items():
+        ephi, eE = rel(g, d)
+        say(f"[large] plummer134m precision {prec}: phi {ephi:.2e} E {eE:.2e}")
+        assert ephi <= 1e-6 and eE <= 1e-6
