@@ -126,8 +126,10 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     last = None
-    for _ in range(args.steps):
+    ev_steps = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    for k in range(args.steps):
         tr = step()
+        ev_steps[k].record(stream)
         ph = fmm.fmm_last_timings()
         for k in phase_sum:
             phase_sum[k] += ph[k]
@@ -138,6 +140,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
+    per_step = sorted(a.elapsed_time(b) for a, b in zip([ev0] + ev_steps[:-1], ev_steps))
     m2l_pairs, p2p_pairs = fmm.fmm_tree_stats(last)
     last.free()
     ms_step = ms_total / args.steps
@@ -174,6 +177,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "step_ms": {"median": round(float(np.median(per_step)), 4), "min": round(per_step[0], 4),
+                    "max": round(per_step[-1], 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
