@@ -92,52 +92,60 @@ def test_plummer16m_full_size(torch, F):
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer16m_grid.json")
 
 
-def test_plummer16m_theta_p_grid(torch, F):
+@pytest.fixture(scope="module")
+def plummer16m(torch, F):
+    """The workload on the device, 10,000 sampled indices, the direct sum
+    there, and the oracle's stored grid values by theta."""
+    x, y, z, q, w = W.workload("plummer16m")
+    n = x.shape[0]
+    X, Y, Z, Q = (dev(torch, a) for a in (x, y, z, q))
+    tg = W.sample_targets(n, 10_000, seed=1)
+    idx = torch.from_numpy(tg).to("cuda")
+    d = direct_at(torch, F, X, Y, Z, Q, idx)
+    with open(GOLDEN) as f:
+        golden = {row["theta"]: row for row in json.load(f)["grid"]}
+    return X, Y, Z, Q, w["levels"], idx, d, golden
+
+
+@pytest.mark.parametrize("theta", (0.4, 0.5, 0.6))
+def test_plummer16m_theta_p_grid(torch, F, plummer16m, theta):
     """The clustered-cloud grid: theta in {0.4, 0.5, 0.6} x p in {8, 12, 16},
     binary64 and (p <= 15) mixed precision.  Against the oracle's values on
     sampled leaves (tests/golden/plummer16m_grid.json, written by the oracle
     alone): binary64 within FP64_TOL, mixed within 1e-6.  Errors against the
     direct sum at 10,000 sampled points are printed; the error falls with p
     at fixed theta, and p 12 reaches 1e-6 at theta 0.5."""
-    x, y, z, q, w = W.workload("plummer16m")
-    n, L = x.shape[0], w["levels"]
-    X, Y, Z, Q = (dev(torch, a) for a in (x, y, z, q))
-    tg = W.sample_targets(n, 10_000, seed=1)
-    idx = torch.from_numpy(tg).to("cuda")
-    d = direct_at(torch, F, X, Y, Z, Q, idx)
+    X, Y, Z, Q, L, idx, d, golden = plummer16m
     o = [torch.empty_like(X) for _ in range(4)]
-    with open(GOLDEN) as f:
-        golden = {row["theta"]: row for row in json.load(f)["grid"]}
 
     def run(gt, p, prec):
         F.fmm_evaluate_tree(gt, Q, p, *o, precision=prec)
         torch.cuda.synchronize()
         return [a.index_select(0, idx).cpu().numpy() for a in o]
 
-    for theta in (0.4, 0.5, 0.6):
-        gt = F.fmm_build(X, Y, Z, L, theta)
-        gold = golden[theta]
-        gidx = torch.tensor(gold["index"], dtype=torch.int64, device="cuda")
-        errs = {}
-        for p in (8, 12, 16):
-            g64 = run(gt, p, F.FMM_PREC_F64)
-            ref = [np.array(gold["orders"][str(p)][k]) for k in ("phi", "ex", "ey", "ez")]
-            at = [a.index_select(0, gidx).cpu().numpy() for a in o]
-            assert_close(at, ref, what=f"plummer16m theta {theta} p {p} vs oracle")
-            errs[p] = max(rel(g64, d))
-            line = f"[grid] theta {theta} p {p}: binary64 {errs[p]:.2e}"
-            if p <= 15:
-                g32 = run(gt, p, F.FMM_PREC_MIXED)
-                at32 = [a.index_select(0, gidx).cpu().numpy() for a in o]
-                assert_close(at32, ref, tol=1e-6, what=f"plummer16m theta {theta} p {p} mixed vs oracle")
-                line += f" mixed {max(rel(g32, d)):.2e} mixed-vs-f64 {max(rel(g32, g64)):.2e}"
-                assert max(rel(g32, g64)) <= 1e-6
-            say(line)
-        ps = sorted(errs)
-        assert all(errs[a] > errs[b] for a, b in zip(ps, ps[1:]))
-        if theta == 0.5:
-            assert errs[12] <= 1e-6
-        gt.free()
+    gt = F.fmm_build(X, Y, Z, L, theta)
+    gold = golden[theta]
+    gidx = torch.tensor(gold["index"], dtype=torch.int64, device="cuda")
+    errs = {}
+    for p in (8, 12, 16):
+        g64 = run(gt, p, F.FMM_PREC_F64)
+        ref = [np.array(gold["orders"][str(p)][k]) for k in ("phi", "ex", "ey", "ez")]
+        at = [a.index_select(0, gidx).cpu().numpy() for a in o]
+        assert_close(at, ref, what=f"plummer16m theta {theta} p {p} vs oracle")
+        errs[p] = max(rel(g64, d))
+        line = f"[grid] theta {theta} p {p}: binary64 {errs[p]:.2e}"
+        if p <= 15:
+            g32 = run(gt, p, F.FMM_PREC_MIXED)
+            at32 = [a.index_select(0, gidx).cpu().numpy() for a in o]
+            assert_close(at32, ref, tol=1e-6, what=f"plummer16m theta {theta} p {p} mixed vs oracle")
+            line += f" mixed {max(rel(g32, d)):.2e} mixed-vs-f64 {max(rel(g32, g64)):.2e}"
+            assert max(rel(g32, g64)) <= 1e-6
+        say(line)
+    ps = sorted(errs)
+    assert all(errs[a] > errs[b] for a, b in zip(ps, ps[1:]))
+    if theta == 0.5:
+        assert errs[12] <= 1e-6
+    gt.free()
 
 
 def test_plummer134m_full_size(torch, F):
