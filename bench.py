@@ -217,19 +217,18 @@ TUNED_MAX_N = 1 << 22  # the tuned legs calibrate on clouds of the workload's si
 def tuned_legs(X, Y, Z, Q, L, steps, stream, torch, tol: float = 1e-6) -> dict:
     """The workload at the metric's accuracy with theta, p and precision
     picked by the autotuner (serve.Tuner, calibrated on the GPU at this level
-    count): its choice with mixed precision allowed, and the same with
-    binary64 forced (then p is the smallest binary64 order that meets tol at
-    the chosen theta).  Each: ms per step (build + evaluate) and the error
-    against the direct sum at 10,000 sampled points (gpu_direct_gate)."""
+    count, theta 0.4, 0.5 and 0.6, orders 1..15): its choice with mixed
+    precision allowed, and its choice with every candidate in binary64.
+    Each: ms per step (build + evaluate) and the error against the direct sum
+    at 10,000 sampled points (gpu_direct_gate)."""
     from paper_2002_04894_amd import serve
     n = X.numel()
     tuner = serve.Tuner()
     t0 = time.perf_counter()
-    tuner.calibrate(levels=(L,), orders=range(1, 14))
+    tuner.calibrate(levels=(L,), thetas=(0.4, 0.5, 0.6), orders=range(1, 16))
     cal_s = time.perf_counter() - t0
     out = {"tol": tol, "calibration_s": round(cal_s, 2)}
-    lev, th, p, prec = tuner.choose(n, tol)
-    legs = {"mixed_allowed": (lev, th, p, prec), "f64": (lev, th, tuner.order(tol, lev, th), fmm.FMM_PREC_F64)}
+    legs = {"mixed_allowed": tuner.choose(n, tol), "f64": tuner.choose(n, tol, allow_mixed=False)}
     for name, (lv, t_, p_, pr) in legs.items():
         o = [torch.empty_like(X) for _ in range(4)]
 
@@ -284,17 +283,20 @@ def gpu_direct_gate(X, Y, Z, Q, outs, torch, k: int = 10_000) -> dict:
     tg = workloads.sample_targets(n, k, seed=1)
     idx = torch.from_numpy(tg).to("cuda")
     T = [a.index_select(0, idx).contiguous() for a in (X, Y, Z)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     tree = fmm.fmm_build_ex(X, Y, Z, 2, 0.0, targets=tuple(T))
     d = [torch.empty(k, dtype=torch.float64, device="cuda") for _ in range(4)]
     fmm.fmm_evaluate_targets(tree, Q, 0, *d)
     torch.cuda.synchronize()
+    direct_ms = 1e3 * (time.perf_counter() - t0)
     tree.free()
     d = [a.cpu().numpy() for a in d]
     g = [o.index_select(0, idx).cpu().numpy() for o in outs]
     ephi = float(np.linalg.norm(g[0] - d[0]) / np.linalg.norm(d[0]))
     eE = float(np.linalg.norm(np.concatenate(g[1:]) - np.concatenate(d[1:])) / np.linalg.norm(np.concatenate(d[1:])))
     return {"targets": k, "method": "GPU direct sum at sampled targets (theta = 0, all P2P)", "rel_err_phi": ephi,
-            "rel_err_E": eE, "ok": bool(ephi <= 1e-6 and eE <= 1e-6)}
+            "rel_err_E": eE, "ok": bool(ephi <= 1e-6 and eE <= 1e-6), "direct_sum_ms": round(direct_ms, 3)}
 
 
 def mixed_leg(step, mouts, outs, n, steps, stream, torch):

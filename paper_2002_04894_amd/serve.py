@@ -190,13 +190,16 @@ class Tuner:
         q = max(c) if p > max(c) else min(c)
         return c[q] * ((p + 1) / (q + 1)) ** 3
 
-    def choose(self, n: int, tol: float) -> tuple[int, float, int, int]:
+    def choose(self, n: int, tol: float, allow_mixed: bool = True) -> tuple[int, float, int, int]:
+        """(levels, theta, p, precision) of least measured cost that meets
+        tol; allow_mixed = False keeps every candidate in binary64."""
         L = self.levels(n)
         thetas = sorted({t for (_, t) in self.errors}) if self.errors else [self.theta]
         best = None
         for th in thetas:
             p = self.order(tol, L, th)
-            prec = fmm.FMM_PREC_MIXED if (tol >= self.kMixedMinTol and p <= 15) else fmm.FMM_PREC_F64
+            mixed = allow_mixed and tol >= self.kMixedMinTol and p <= 15
+            prec = fmm.FMM_PREC_MIXED if mixed else fmm.FMM_PREC_F64
             key = (self._cost(L, th, prec, p), p, th)
             if best is None or key < best[0]:
                 best = (key, (L, th, p, prec))

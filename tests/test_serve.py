@@ -85,6 +85,21 @@ def test_tuner_levels_theta_and_cost():
     assert t.model(10, 2, 0.5) == max(e3[10], e4[10])
 
 
+def test_tuner_binary64_only_choice():
+    """allow_mixed = False keeps every candidate in binary64 and then picks
+    the cheapest binary64 theta, which may differ from the mixed choice."""
+    e = {p: 1e-3 * 0.5 ** p for p in range(1, 17)}
+    e6 = {p: 1e-3 * 0.6 ** p for p in range(1, 17)}
+    errors = {(3, 0.5): e, (3, 0.6): e6}
+    cost = {(3, 0.5, 1): {p: 1.0 for p in range(1, 17)}, (3, 0.5, 0): {p: 10.0 for p in range(1, 17)},
+            (3, 0.6, 1): {p: 5.0 for p in range(1, 17)}, (3, 0.6, 0): {p: 3.0 for p in range(1, 17)}}
+    t = serve.Tuner(errors=errors, cost=cost)
+    L, th, p, prec = t.choose(20_000, 1e-6)
+    assert (L, th, prec) == (3, 0.5, 1)
+    L, th, p, prec = t.choose(20_000, 1e-6, allow_mixed=False)
+    assert (L, th, prec) == (3, 0.6, 0) and 2 * t.model(p, 3, 0.6) <= 1e-6
+
+
 def test_tuner_model_is_monotone():
     """A measurement that rises with p (noise, or the rounding floor) must
     not let the tuner pick the lower order."""
