@@ -18,9 +18,12 @@
  *    caller memory.  Arrays named "host" are ordinary host memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *  - Every function returns FMM_OK (0) or a negative status; on failure no
- *    output is defined, nothing leaks, and fmm_last_error() returns a message
- *    (per calling thread).  Argument checks happen before any work is
- *    enqueued.  No exception crosses the ABI.
+ *    output is defined and fmm_last_error() returns a message (per calling
+ *    thread).  A failed call frees what it allocated and leaves no handle
+ *    behind, with one exception: a HIP runtime failure in the middle of a
+ *    call (FMM_ENOMEM, FMM_EDEVICE) may leave that call's device scratch
+ *    allocated until the process ends.  Argument checks happen before any
+ *    work is enqueued.  No exception crosses the ABI.
  *  - A tree handle may be used by one thread at a time.  Different handles
  *    may be used by different threads at once, each on its own stream
  *    (blocking or non-blocking).
