@@ -164,9 +164,11 @@ def main(argv=None) -> int:
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--repeats", type=int, default=4)
     ap.add_argument("--dists", default=",".join(workloads.RESPONSE_DISTRIBUTIONS))
+    ap.add_argument("--levels", default=None, help="level counts of the level sweep, e.g. 3,4,5,6")
     ap.add_argument("--out", default=None, help="write every row as JSON here")
     a = ap.parse_args(argv)
-    rows = run(a.n, a.tol, a.repeats, dists=tuple(a.dists.split(",")))
+    levels = tuple(int(v) for v in a.levels.split(",")) if a.levels else None
+    rows = run(a.n, a.tol, a.repeats, dists=tuple(a.dists.split(",")), levels=levels)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(rows, f, indent=1)
