@@ -171,6 +171,16 @@ __host__ __device__ constexpr Pos slot_pos(int t, int s) {
   return s <= P ? Pos{1, P, s} : Pos{0, 0, 0};
 }
 
+// 1 if k-step k of tile t (slots 4k .. 4k+3) holds a coefficient position.
+// A step of padding slots only multiplies zero operator columns, so the J
+// products skip it (below order 12 the last step of every pair tile).
+template <int P>
+__host__ __device__ constexpr bool kstep_used(int t, int k) {
+  for (int g = 0; g < 4; ++g)
+    if (slot_pos<P>(t, 4 * k + g).pos) return true;
+  return false;
+}
+
 // The four lanes groups g = 0..3 hold slots 4i + g of register i.  Along g
 // they form at most three runs: within a run either padding, or one degree n
 // with orders m = m0 + g.
@@ -290,7 +300,8 @@ __device__ __forceinline__ void japply(typename Ar<R>::v4* st, const R* jr) {
     if (tile_owner<P>(t) != W) continue;
     typename Ar<R>::v4 d = {0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) d = mfma(jr[t * 4 + k], st[t][k], d);
+    for (int k = 0; k < 4; ++k)
+      if (kstep_used<P>(t, k)) d = mfma(jr[t * 4 + k], st[t][k], d);
     st[t] = d;
   }
 }
@@ -399,7 +410,7 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
   for (int t = 0; t < T; ++t)
     if (tile_owner<P>(t) == W)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) jr[t * 4 + k] = mtab[(t * 4 + k) * 64 + lane];
+      for (int k = 0; k < 4; ++k) jr[t * 4 + k] = kstep_used<P>(t, k) ? mtab[(t * 4 + k) * 64 + lane] : (R)0;
   R hr[C::H];
 #pragma unroll
   for (int m = 0; m <= P; ++m)
