@@ -29,15 +29,16 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one M2L launch on the 2^20-point mixture (p 15), from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) of
-# `bench.py --steps 1 --warmup 0 --no-cpu`, scaled by the same counters on a
+# `bench.py --steps 1 --warmup 0 --no-cpu --mixed-steps 0 --serve-requests 0
+# --tuned-steps 0`, scaled by the same counters on a
 # 1 GiB device copy (`bench.py --copy-bytes 1073741824`): FETCH_SIZE read
 # 524308 KiB and WRITE_SIZE 1048576 KiB for 1048576 KiB moved each way.
 # Valid only for the kernel source it was taken on (hash below).
 M2L_COUNTERS = {
-    "sources_sha256": "5b63c488d0e5bf3415dca20155f37c0e7d08c0ad0b41db571aea9a84dde0f060",
+    "sources_sha256": "83a1c2f950a6c294e89987b3a6d7952fc8f6c6895f8b908f79bcf5cbb3c9ead8",
     "workload": "gmix1m",
-    "fetch_kib": 141123022.125,
-    "write_kib": 1053351.1875,
+    "fetch_kib": 141174313.125,
+    "write_kib": 1053250.8125,
     "fetch_scale": 1048576.0 / 524308.4375,
     "write_scale": 1.0,
 }
