@@ -181,6 +181,13 @@ __host__ __device__ constexpr bool kstep_used(int t, int k) {
   return false;
 }
 
+// 1 if register i of tile t holds padding slots only (then the J products
+// give it zeros, and the rotations and the z translation leave it alone).
+template <int P>
+__host__ __device__ constexpr bool all_pad(int t, int i) {
+  return !kstep_used<P>(t, i);
+}
+
 // The four lanes groups g = 0..3 hold slots 4i + g of register i.  Along g
 // they form at most three runs: within a run either padding, or one degree n
 // with orders m = m0 + g.
@@ -241,6 +248,7 @@ __device__ __forceinline__ void rotz(typename Ar<R>::v4* st, const R* cs, R sgn,
   }
   auto rot = [&](R& c, R& s, int t, int i) {
     const Quad q = quad<P>(t, i);
+    if (q.nseg == 1 && q.pad[0]) return;  // padding only: nothing to rotate
     const int k0 = 2 * (q.m0[0] + 4), k1 = 2 * (q.m0[1] + 4), k2 = 2 * (q.m0[2] + 4);
     // a padding run reads any finite entry: its coefficients are zero
     const v2 v = *(const v2*)(cs + pick(q, g, q.pad[0] ? 8 : k0, q.pad[1] ? 8 : k1, q.pad[2] ? 8 : k2));
@@ -345,7 +353,7 @@ __device__ __forceinline__ void ztrans_part(typename Ar<R>::v4* st, const ZView<
     if (tile_owner<P>(t) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      if (reg_sine<P>(t, i) != SINE) continue;
+      if (reg_sine<P>(t, i) != SINE || all_pad<P>(t, i)) continue;
       *zslot<P, R>(z, t, i, g, false) = st[t][i];
     }
   }
@@ -372,7 +380,7 @@ __device__ __forceinline__ void ztrans_part(typename Ar<R>::v4* st, const ZView<
     if (tile_owner<P>(t) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      if (reg_sine<P>(t, i) != SINE) continue;
+      if (reg_sine<P>(t, i) != SINE || all_pad<P>(t, i)) continue;
       st[t][i] = *zslot<P, R>(z, t, i, g, true);
     }
   }
