@@ -35,10 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # 524308 KiB and WRITE_SIZE 1048576 KiB for 1048576 KiB moved each way.
 # Valid only for the kernel source it was taken on (hash below).
 M2L_COUNTERS = {
-    "sources_sha256": "83a1c2f950a6c294e89987b3a6d7952fc8f6c6895f8b908f79bcf5cbb3c9ead8",
+    "sources_sha256": "505751c1cb651985704f757fe09a48b2d0e23d888f4d7e6706317efd10ae9ab7",
     "workload": "gmix1m",
-    "fetch_kib": 141174313.125,
-    "write_kib": 1053250.8125,
+    "fetch_kib": 142384087.6875,
+    "write_kib": 1016343.9375,
     "fetch_scale": 1048576.0 / 524308.4375,
     "write_scale": 1.0,
 }
