@@ -476,3 +476,68 @@ def test_fmm_linear_in_charges(orc):
     a = t.evaluate(q1, 6); b = t.evaluate(q2, 6); c = t.evaluate(q1 + 2 * q2, 6)
     for u, v, w in zip(a, b, c):
         assert np.allclose(u + 2 * v, w, rtol=0, atol=1e-12 * np.abs(w).max())
+
+
+# --------------------------------------------------------------------------
+# Whole FMM at three and four levels: the downward pass (Algorithm 3, L2L)
+# --------------------------------------------------------------------------
+
+def _chain_weak(t, levels, leaves):
+    """Weak-list entries of the ancestors of `leaves`, per level 1..L."""
+    out = {}
+    for l in range(1, levels + 1):
+        off, _ = t.lists(l, 1)
+        anc = np.unique(np.asarray(leaves) // 8 ** (levels - l))
+        out[l] = int(sum(off[a + 1] - off[a] for a in anc))
+    return out
+
+
+@pytest.mark.parametrize("gen,n,levels,p,theta", [
+    ("cube", 4000, 3, 10, 0.5),
+    ("gmix", 4000, 3, 10, 0.5),
+    ("cube", 6000, 4, 12, 0.5),
+    ("gmix", 6000, 4, 12, 0.5),
+    ("gmix", 6000, 4, 10, 0.4),
+])
+def test_fmm_deep_tree_matches_direct_sum(orc, gen, n, levels, p, theta):
+    """With L >= 3 the ancestors of a leaf at levels 2..L-1 hold local
+    expansions of their own (weak pairs there), which reach the leaf only
+    through L2L.  A wrong L2L (sign of the shift, index, missing term) leaves
+    an error far above the truncation error; this is the only whole-method
+    check of the downward pass on the CPU.  Every point of 12 sampled leaves
+    is compared with the direct sum, eq. (2.1)."""
+    make = W.uniform_cube if gen == "cube" else W.gaussian_mixture
+    x, y, z, q = make(n, seed=5)
+    t = orc.Tree(x, y, z, levels, theta)
+    leaves = np.sort(np.random.default_rng(3).choice(8 ** levels, 12, replace=False))
+    weak = _chain_weak(t, levels, leaves)
+    assert any(weak[l] > 0 for l in range(2, levels)), weak
+    f = t.evaluate(q, p, leaves=leaves)
+    s, perm = t.start(levels), t.perm()
+    pts = np.concatenate([perm[s[b]:s[b + 1]] for b in leaves])
+    assert pts.size > 0
+    d = orc.direct(x, y, z, q, targets=pts)
+    for u, v in zip(f, d):
+        assert _relerr(u[pts], v) < 1e-6
+    # the far field alone is far from zero at these points: the test sees it
+    far = t.evaluate(q, p, parts=2, leaves=leaves)
+    assert np.linalg.norm(far[0][pts]) > 1e-2 * np.linalg.norm(d[0])
+
+
+@pytest.mark.parametrize("levels,p", [(3, 12), (4, 12)])
+def test_fmm_deep_tree_separate_targets_match_direct_sum(orc, levels, p):
+    """The same at separate evaluation points (Section 3.1 evaluates at
+    points that are not sources): L2P + P2P at the target's leaf, whose local
+    expansion is built through L2L from levels 2..L-1."""
+    x, y, z, q = W.gaussian_mixture(5000, seed=9)
+    tx, ty, tz, _ = W.gaussian_mixture(150, seed=10)  # same cloud shape, other points
+    t = orc.Tree(x, y, z, levels, 0.5, targets=(tx, ty, tz))
+    leaves = np.unique([t.locate(a, b, c) for a, b, c in zip(tx, ty, tz)])
+    weak = _chain_weak(t, levels, leaves)
+    assert any(weak[l] > 0 for l in range(2, levels)), weak
+    f = t.evaluate_targets(q, p)
+    # direct sum at the targets: add them as zero-charge sources
+    X = np.r_[x, tx]; Y = np.r_[y, ty]; Z = np.r_[z, tz]; Q = np.r_[q, np.zeros(tx.size)]
+    d = orc.direct(X, Y, Z, Q, targets=np.arange(x.size, x.size + tx.size))
+    for u, v in zip(f, d):
+        assert _relerr(u, v) < 1e-6
