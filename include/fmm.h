@@ -17,16 +17,21 @@
  *    the work enqueued on `stream` has completed; the library never frees
  *    caller memory.  Arrays named "host" are ordinary host memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *  - Every function returns FMM_OK (0) or a negative status; on failure no
- *    output is defined and fmm_last_error() returns a message (per calling
- *    thread).  A failed call frees what it allocated and leaves no handle
- *    behind, with one exception: a HIP runtime failure in the middle of a
- *    call (FMM_ENOMEM, FMM_EDEVICE) may leave that call's device scratch
- *    allocated until the process ends.  Argument checks happen before any
- *    work is enqueued.  No exception crosses the ABI.
+ *  - Every function returns FMM_OK (0) or a negative fmm_status; on failure
+ *    no output is defined and fmm_last_error() returns a message (per
+ *    calling thread).  A failed call frees every device allocation it made
+ *    (stream-ordered on its stream) and leaves no new handle behind; a tree
+ *    passed to a failed evaluation stays valid and can be evaluated again or
+ *    freed.  Argument checks happen before any work is enqueued.  No
+ *    exception crosses the ABI.
+ *  - Device memory comes from the allocator set by fmm_set_allocator, else
+ *    from the device's default stream-ordered pool.
  *  - A tree handle may be used by one thread at a time.  Different handles
  *    may be used by different threads at once, each on its own stream
- *    (blocking or non-blocking).
+ *    (blocking or non-blocking).  A tree may be evaluated on any stream: an
+ *    evaluation on another stream than the build's waits (on the device) for
+ *    the build, and fmm_free waits (on the device) for every evaluation
+ *    enqueued on the tree before its memory is released.
  *  - The first evaluation at an order p on a device makes that order's
  *    operator tables (kept until the process ends) and waits for `stream`
  *    once, so that the tables are on the device before any stream uses them;
@@ -44,13 +49,13 @@ extern "C" {
 
 typedef struct fmm_tree fmm_tree;
 
-enum fmm_status {
+typedef enum fmm_status {
   FMM_OK = 0,
   FMM_EINVAL = -1,       /* invalid argument (NULL pointer, range, non-finite coordinate) */
   FMM_ENOMEM = -2,       /* device or host allocation failed */
   FMM_EDEVICE = -3,      /* HIP runtime error (no device, launch failure, ...) */
   FMM_EUNSUPPORTED = -4  /* valid request that the library does not support */
-};
+} fmm_status;
 
 #define FMM_MAX_LEVELS 8
 #define FMM_MAX_ORDER 20
@@ -61,6 +66,28 @@ enum fmm_status {
 #define FMM_PART_NEAR 1
 #define FMM_PART_FAR 2
 #define FMM_PART_ALL 3
+
+/*
+ * Device allocator hook (the paper's solver is meant as a plug-in for other
+ * applications, Section 2.2.2: a host application brings its own memory
+ * manager, e.g. the caching allocator of PyTorch).
+ *   alloc(bytes, stream, user)  returns device memory usable by work enqueued
+ *                               on `stream` (a hipStream_t), or NULL on failure;
+ *                               the library then fails the call with
+ *                               FMM_ENOMEM and frees what it allocated.
+ *   free(ptr, stream, user)     releases a block; work enqueued on `stream`
+ *                               before the call may still read it, so a
+ *                               stream-ordered allocator must not hand the
+ *                               block out again before that work completes.
+ * Both must be thread-safe when handles are used from several threads.
+ * Passing alloc = free = NULL restores the default pool.  A tree keeps the
+ * allocator it was built with and is freed through it; scratch memory of an
+ * evaluation comes from the allocator set at the time of the call.  Returns
+ * FMM_EINVAL when exactly one of alloc and free is NULL.
+ */
+typedef void* (*fmm_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*fmm_free_fn)(void* ptr, void* stream, void* user);
+fmm_status fmm_set_allocator(fmm_alloc_fn alloc, fmm_free_fn free, void* user);
 
 /*
  * Builds the tree (Section 2.1.2 and Algorithm 2 on one process).
@@ -74,7 +101,7 @@ enum fmm_status {
  * list sizes are read back to size the lists).  Non-finite coordinates give
  * FMM_EINVAL.
  */
-int fmm_build(const double* x, const double* y, const double* z, int64_t n, int levels, double theta,
+fmm_status fmm_build(const double* x, const double* y, const double* z, int64_t n, int levels, double theta,
               void* stream, fmm_tree** out);
 
 /*
@@ -85,13 +112,13 @@ int fmm_build(const double* x, const double* y, const double* z, int64_t n, int 
  *   pot, ex, ey, ez        device, n doubles each, written in the caller's order.
  * Fully asynchronous on `stream`; may be called many times on one tree.
  */
-int fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, double* ex, double* ey, double* ez,
+fmm_status fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, double* ex, double* ey, double* ez,
                       void* stream);
 
 /* As fmm_evaluate_tree, but writes only the near-field (P2P) part, the
  * far-field (L2P) part, or both (FMM_PART_*): used to check each half of
  * Algorithm 4 separately. */
-int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
+fmm_status fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
                             double* ez, void* stream);
 
 /* Arithmetic of the evaluation (fmm_evaluate_tree_ex). */
@@ -111,7 +138,7 @@ int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, d
  * (normwise) on the workloads tested.  Higher orders run in binary64.
  * Returns FMM_EINVAL for an unknown precision.
  */
-int fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+fmm_status fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
                          double* ey, double* ez, void* stream);
 
 /*
@@ -139,7 +166,7 @@ int fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int 
  * segment of the round before held at least 8192 points and the round has
  * at most 512 segments (the segment sizes choose the round's kernels).
  */
-int fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, const double* tx, const double* ty,
+fmm_status fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, const double* tx, const double* ty,
                  const double* tz, int64_t m, int levels, double theta, double eta, void* stream, fmm_tree** out);
 
 /*
@@ -153,21 +180,21 @@ int fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, c
  *                      target order (may be NULL when m = 0).
  * Fully asynchronous on `stream`.  A tree without targets does nothing.
  */
-int fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+fmm_status fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
                          double* ey, double* ez, void* stream);
 
 /* Number of separate targets of a tree and, when `leaf` (host, m int32) is
  * not NULL, the leaf that holds each of them (caller's target order). */
-int fmm_tree_targets(const fmm_tree* tree, int64_t* m, int32_t* leaf);
+fmm_status fmm_tree_targets(const fmm_tree* tree, int64_t* m, int32_t* leaf);
 
 /* One-shot form: fmm_build + fmm_evaluate_tree + fmm_free.  All arrays are
  * device arrays of n doubles. */
-int fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,
+fmm_status fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,
                  int levels, double* pot, double* ex, double* ey, double* ez, void* stream);
 
 /* Releases a handle and its device memory (stream-ordered on the stream of the
  * last call that used it).  NULL is accepted. */
-int fmm_free(fmm_tree* tree);
+fmm_status fmm_free(fmm_tree* tree);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* fmm_last_error(void);
@@ -175,16 +202,16 @@ const char* fmm_last_error(void);
 /* ---- Introspection (used by parity tests; synchronous, host outputs) ---- */
 
 /* n, levels and theta of a tree (any output pointer may be NULL). */
-int fmm_tree_info(const fmm_tree* tree, int64_t* n, int* levels, double* theta);
+fmm_status fmm_tree_info(const fmm_tree* tree, int64_t* n, int* levels, double* theta);
 
 /* host perm[n]: original index of the point at each tree position.  Points
  * of every leaf occupy a contiguous range in ascending original index. */
-int fmm_tree_perm(const fmm_tree* tree, int32_t* perm);
+fmm_status fmm_tree_perm(const fmm_tree* tree, int32_t* perm);
 
 /* host geom[8^level * 10]: per box lo[3], hi[3], centre[3], radius (cell
  * centre and half-diagonal, Section 2.1.1), and host start[8^level + 1]:
  * point range of each box in tree order (either pointer may be NULL). */
-int fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start);
+fmm_status fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start);
 
 /* Connectivity of one level (Section 2.2.1: per-level sparse connectivity),
  * as CSR by target box, ascending source box index within each row.
@@ -192,12 +219,12 @@ int fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start
  *   nnz      host, receives the number of entries.
  *   offsets  host, 8^level + 1 entries, or NULL.
  *   idx      host, nnz entries (box indices of that level), or NULL. */
-int fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int64_t* offsets, int32_t* idx);
+fmm_status fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int64_t* offsets, int32_t* idx);
 
 /* Work counts of a tree: M2L translations (weak pairs over all levels) and
  * P2P interactions (ordered point pairs in strongly connected leaves, minus
  * the n self pairs). */
-int fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs);
+fmm_status fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs);
 
 /* ---- Phase timing ------------------------------------------------------ */
 
@@ -215,15 +242,22 @@ enum fmm_phase {
 };
 
 /* Turns event timing on (1) or off (0) for subsequent calls on this thread. */
-int fmm_set_profiling(int on);
+fmm_status fmm_set_profiling(int on);
 
 /* host ms[FMM_NUM_PHASES]: durations of the phases of the most recent
  * fmm_build / fmm_evaluate_tree on this thread (0 for phases not run).
  * Waits for those events. */
-int fmm_last_timings(double* ms);
+fmm_status fmm_last_timings(double* ms);
+
+/* Device memory of a built tree: *tree_bytes (may be NULL) receives the
+ * bytes the handle owns (tree, lists, plans); *eval_bytes (may be NULL) the
+ * peak scratch bytes one evaluation at order p and the given precision
+ * allocates on top (sources, and the separate targets when the tree has
+ * them).  Unlike fmm_bytes_estimate these are exact, for any point cloud. */
+fmm_status fmm_tree_bytes(const fmm_tree* tree, int p, int precision, size_t* tree_bytes, size_t* eval_bytes);
 
 /* Estimate of the device bytes a build + evaluation needs, for admission
- * control.  The interaction lists are sized as for a uniform cloud, so the
+ * control before a build.  The interaction lists are sized as for a uniform cloud, so the
  * estimate bounds roughly uniform data from above; on strongly clustered
  * clouds the lists can be more than ten times larger (2^27 Plummer points of
  * scale radius 0.02 at 7 levels: 2.2e10 weak pairs against 1.8e9 list

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <mutex>
 
 #include "fmm_internal.h"
@@ -32,15 +33,80 @@ void init_pool() {
   }
 }
 
+// the process-wide allocator hook (fmm_set_allocator)
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  return g_alloc;
+}
+
+void* raw_alloc(const Allocator& a, size_t bytes, hipStream_t s) {
+  void* p = nullptr;
+  if (a.alloc) {
+    p = a.alloc(bytes, (void*)s, a.user);
+  } else {
+    std::call_once(g_pool_once, init_pool);
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+  }
+  return p;
+}
+
+void raw_free(const Allocator& a, void* p, hipStream_t s) {
+  if (!p) return;
+  if (a.free)
+    a.free(p, (void*)s, a.user);
+  else
+    (void)hipFreeAsync(p, s);
+}
+
+// The allocations of one entry-point call: a failed call frees those still
+// live; a successful build hands them to its tree.
+struct Ledger {
+  Allocator a;
+  std::vector<std::pair<void*, size_t>> live;
+};
+thread_local Ledger* g_ledger = nullptr;
+
+class CallScope {
+ public:
+  CallScope(const Allocator& a, hipStream_t s) : s_(s), prev_(g_ledger) {
+    led_.a = a;
+    g_ledger = &led_;
+  }
+  ~CallScope() {
+    if (!kept_)
+      for (auto it = led_.live.rbegin(); it != led_.live.rend(); ++it) raw_free(led_.a, it->first, s_);
+    g_ledger = prev_;
+  }
+  // the live allocations now belong to the caller (a tree); returns their bytes
+  size_t keep() {
+    kept_ = true;
+    size_t b = 0;
+    for (auto& e : led_.live) b += e.second;
+    return b;
+  }
+
+ private:
+  Ledger led_;
+  hipStream_t s_;
+  Ledger* prev_;
+  bool kept_ = false;
+};
+
 template <class F>
-int guarded(F&& f) {
+fmm_status guarded(F&& f) {
   try {
     f();
     g_err.clear();
     return FMM_OK;
   } catch (const Error& e) {
     set_err(e.msg);
-    return e.code;
+    return (fmm_status)e.code;
   } catch (const std::bad_alloc&) {
     set_err("host allocation failed");
     return FMM_ENOMEM;
@@ -50,25 +116,30 @@ int guarded(F&& f) {
   }
 }
 
+// Frees the tree's memory through its allocator on the stream of its last
+// use, after that stream has waited for every other stream that used it.
 void release(Tree& t) {
   hipStream_t s = t.stream;
-  auto f = [&](void* p) {
-    if (p) (void)hipFreeAsync(p, s);
-  };
+  for (auto& u : t.uses) {
+    if (u.first != s) (void)hipStreamWaitEvent(s, u.second, 0);
+    (void)hipEventDestroy(u.second);
+  }
+  t.uses.clear();
+  if (t.built) {
+    if (t.build_stream != s) (void)hipStreamWaitEvent(s, t.built, 0);
+    (void)hipEventDestroy(t.built);
+    t.built = nullptr;
+  }
+  auto f = [&](void* p) { raw_free(t.alloc, p, s); };
   f(t.px);
   f(t.py);
   f(t.pz);
   f(t.perm);
   f(t.m2l_order);
-  t.m2l_order = nullptr;
   f(t.p2p_seg_leaf);
   f(t.p2p_seg_e0);
   f(t.p2p_leaf_seg);
   f(t.p2p_leaf_part);
-  t.p2p_seg_leaf = nullptr;
-  t.p2p_seg_e0 = nullptr;
-  t.p2p_leaf_seg = nullptr;
-  t.p2p_leaf_part = nullptr;
   f(t.tx);
   f(t.ty);
   f(t.tz);
@@ -76,9 +147,6 @@ void release(Tree& t) {
   f(t.tleaf);
   f(t.tstart);
   f(t.p2p_leaf_tpart);
-  t.tx = t.ty = t.tz = nullptr;
-  t.tperm = t.tleaf = t.tstart = nullptr;
-  t.p2p_leaf_tpart = nullptr;
   for (Level& V : t.lev) {
     f(V.geom);
     f(V.start);
@@ -90,6 +158,31 @@ void release(Tree& t) {
   t.lev.clear();
   t.px = t.py = t.pz = nullptr;
   t.perm = nullptr;
+  t.m2l_order = nullptr;
+  t.p2p_seg_leaf = nullptr;
+  t.p2p_seg_e0 = nullptr;
+  t.p2p_leaf_seg = nullptr;
+  t.p2p_leaf_part = nullptr;
+  t.tx = t.ty = t.tz = nullptr;
+  t.tperm = t.tleaf = t.tstart = nullptr;
+  t.p2p_leaf_tpart = nullptr;
+}
+
+// An evaluation on stream s: s first waits for the build when it is another
+// stream; afterwards the evaluation is recorded so that fmm_free can wait.
+void begin_use(Tree& t, hipStream_t s) {
+  if (t.built && s != t.build_stream) HIPCHECK(hipStreamWaitEvent(s, t.built, 0));
+}
+void end_use(Tree& t, hipStream_t s) {
+  hipEvent_t ev = nullptr;
+  for (auto& u : t.uses)
+    if (u.first == s) ev = u.second;
+  if (!ev) {
+    HIPCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    t.uses.emplace_back(s, ev);
+  }
+  HIPCHECK(hipEventRecord(ev, s));
+  t.stream = s;
 }
 
 // ---- phase timer ----
@@ -112,18 +205,43 @@ void check_hip(hipError_t e, const char* what) {
 }
 
 void* dalloc(size_t bytes, hipStream_t s) {
-  std::call_once(g_pool_once, init_pool);
-  void* p = nullptr;
-  const hipError_t e = hipMallocAsync(&p, bytes ? bytes : 8, s);
-  if (e != hipSuccess || !p) {
-    (void)hipGetLastError();
-    fail(FMM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  if (bytes == 0) bytes = 8;
+  const Allocator a = g_ledger ? g_ledger->a : Allocator{};
+  void* p = raw_alloc(a, bytes, s);
+  if (!p) fail(FMM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  if (g_ledger) {
+    try {
+      g_ledger->live.emplace_back(p, bytes);
+    } catch (...) {
+      raw_free(a, p, s);
+      throw;
+    }
   }
   return p;
 }
 
 void dfree(void* p, hipStream_t s) {
-  if (p) HIPCHECK(hipFreeAsync(p, s));
+  if (!p) return;
+  const Allocator a = g_ledger ? g_ledger->a : Allocator{};
+  if (g_ledger) {
+    auto& v = g_ledger->live;
+    for (size_t k = v.size(); k-- > 0;)
+      if (v[k].first == p) {
+        v.erase(v.begin() + (long)k);
+        break;
+      }
+  }
+  raw_free(a, p, s);
+}
+
+int64_t* host_stage() {
+  thread_local int64_t* h = nullptr;
+  if (!h) {
+    void* p = nullptr;
+    HIPCHECK(hipHostMalloc(&p, kStageWords * sizeof(int64_t), hipHostMallocDefault));
+    h = (int64_t*)p;
+  }
+  return h;
 }
 
 LevelView Tree::view() const {
@@ -211,7 +329,7 @@ fmm_tree* build_impl(const double* x, const double* y, const double* z, int64_t 
   if (m < 0 || m > FMM_MAX_POINTS) fail(FMM_EINVAL, "m must be in [0, 2^31-1]");
   if (m > 0 && (!tx || !ty || !tz)) fail(FMM_EINVAL, "target pointer is NULL");
   ensure_device();
-  fmm_tree* h = new fmm_tree();
+  std::unique_ptr<fmm_tree> h(new fmm_tree());
   fmm::Tree& t = h->t;
   t.n = n;
   t.L = levels;
@@ -219,25 +337,45 @@ fmm_tree* build_impl(const double* x, const double* y, const double* z, int64_t 
   t.eta = eta;
   t.m = m;
   t.stream = s;
-  try {
-    fmm::timer().reset();
-    fmm::timer().begin(FMM_PH_TREE, s);
-    fmm::tree_build(t, x, y, z, tx, ty, tz, s);
-    fmm::timer().end(FMM_PH_TREE, s);
-    fmm::timer().begin(FMM_PH_LISTS, s);
-    fmm::lists_build(t, s);
-    fmm::p2p_plan(t, s);
-    if (m > 0) {
-      fmm::targets_build(t, s);
-      fmm::p2p_plan_targets(t, s);
-    }
-    fmm::timer().end(FMM_PH_LISTS, s);
-  } catch (...) {
-    fmm::release(t);
-    delete h;
-    throw;
+  t.build_stream = s;
+  t.alloc = fmm::current_allocator();
+  fmm::CallScope scope(t.alloc, s);  // frees everything allocated here if the build fails
+  fmm::timer().reset();
+  fmm::timer().begin(FMM_PH_TREE, s);
+  fmm::tree_build(t, x, y, z, tx, ty, tz, s);
+  fmm::timer().end(FMM_PH_TREE, s);
+  fmm::timer().begin(FMM_PH_LISTS, s);
+  fmm::lists_build(t, s);
+  fmm::p2p_plan(t, s);
+  if (m > 0) {
+    fmm::targets_build(t, s);
+    fmm::p2p_plan_targets(t, s);
   }
-  return h;
+  fmm::timer().end(FMM_PH_LISTS, s);
+  HIPCHECK(hipEventCreateWithFlags(&t.built, hipEventDisableTiming));
+  HIPCHECK(hipEventRecord(t.built, s));
+  t.bytes = scope.keep();
+  return h.release();
+}
+
+// Runs one evaluation of tree t on stream s with its scratch memory in a
+// call scope (freed if the evaluation fails; the tree stays valid).
+template <class F>
+void run_evaluation(fmm::Tree& t, hipStream_t s, F&& f) {
+  fmm::begin_use(t, s);
+  // recorded also when the evaluation fails part-way: work may be enqueued
+  struct Use {
+    fmm::Tree& t;
+    hipStream_t s;
+    ~Use() {
+      try {
+        fmm::end_use(t, s);
+      } catch (...) {
+      }
+    }
+  } use{t, s};
+  fmm::CallScope scope(fmm::current_allocator(), s);
+  f();
 }
 
 const fmm::Tree& get(const fmm_tree* h) {
@@ -249,7 +387,7 @@ const fmm::Tree& get(const fmm_tree* h) {
 
 extern "C" {
 
-int fmm_build(const double* x, const double* y, const double* z, int64_t n, int levels, double theta, void* stream,
+fmm_status fmm_build(const double* x, const double* y, const double* z, int64_t n, int levels, double theta, void* stream,
               fmm_tree** out) {
   return fmm::guarded([&] {
     if (!out) fail(FMM_EINVAL, "out is NULL");
@@ -258,7 +396,7 @@ int fmm_build(const double* x, const double* y, const double* z, int64_t n, int 
   });
 }
 
-int fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, const double* tx, const double* ty,
+fmm_status fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, const double* tx, const double* ty,
                  const double* tz, int64_t m, int levels, double theta, double eta, void* stream, fmm_tree** out) {
   return fmm::guarded([&] {
     if (!out) fail(FMM_EINVAL, "out is NULL");
@@ -267,7 +405,7 @@ int fmm_build_ex(const double* x, const double* y, const double* z, int64_t n, c
   });
 }
 
-int fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+fmm_status fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
                          double* ey, double* ez, void* stream) {
   return fmm::guarded([&] {
     fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
@@ -276,12 +414,12 @@ int fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int parts, int 
     if (t.m > 0 && (!pot || !ex || !ey || !ez)) fail(FMM_EINVAL, "output pointer is NULL");
     if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
     if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
-    t.stream = (hipStream_t)stream;
-    fmm::evaluate_targets(t, q, p, parts, precision, pot, ex, ey, ez, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    run_evaluation(t, s, [&] { fmm::evaluate_targets(t, q, p, parts, precision, pot, ex, ey, ez, s); });
   });
 }
 
-int fmm_tree_targets(const fmm_tree* tree, int64_t* m, int32_t* leaf) {
+fmm_status fmm_tree_targets(const fmm_tree* tree, int64_t* m, int32_t* leaf) {
   return fmm::guarded([&] {
     const fmm::Tree& t = get(tree);
     if (m) *m = t.m;
@@ -292,49 +430,45 @@ int fmm_tree_targets(const fmm_tree* tree, int64_t* m, int32_t* leaf) {
   });
 }
 
-int fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
+fmm_status fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
                          double* ey, double* ez, void* stream) {
   return fmm::guarded([&] {
     fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
     validate_eval_args(q, p, pot, ex, ey, ez);
     if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
     if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
-    t.stream = (hipStream_t)stream;
-    fmm::evaluate(t, q, p, parts, precision, pot, ex, ey, ez, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    run_evaluation(t, s, [&] { fmm::evaluate(t, q, p, parts, precision, pot, ex, ey, ez, s); });
   });
 }
 
-int fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
+fmm_status fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int parts, double* pot, double* ex, double* ey,
                             double* ez, void* stream) {
   return fmm_evaluate_tree_ex(tree, q, p, parts, FMM_PREC_F64, pot, ex, ey, ez, stream);
 }
 
-int fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, double* ex, double* ey, double* ez,
+fmm_status fmm_evaluate_tree(fmm_tree* tree, const double* q, int p, double* pot, double* ex, double* ey, double* ez,
                       void* stream) {
   return fmm_evaluate_tree_parts(tree, q, p, FMM_PART_ALL, pot, ex, ey, ez, stream);
 }
 
-int fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,
+fmm_status fmm_evaluate(const double* x, const double* y, const double* z, const double* q, int64_t n, double theta, int p,
                  int levels, double* pot, double* ex, double* ey, double* ez, void* stream) {
   return fmm::guarded([&] {
     validate_points(x, y, z, n);
     validate_tree_args(levels, theta);
     validate_eval_args(q, p, pot, ex, ey, ez);
     hipStream_t s = (hipStream_t)stream;
-    fmm_tree* h = build_impl(x, y, z, n, nullptr, nullptr, nullptr, 0, levels, theta, 1.0, s);
-    try {
-      fmm::evaluate(h->t, q, p, FMM_PART_ALL, FMM_PREC_F64, pot, ex, ey, ez, s);
-    } catch (...) {
-      fmm::release(h->t);
-      delete h;
-      throw;
-    }
-    fmm::release(h->t);
-    delete h;
+    std::unique_ptr<fmm_tree> h(build_impl(x, y, z, n, nullptr, nullptr, nullptr, 0, levels, theta, 1.0, s));
+    struct Rel {
+      fmm::Tree& t;
+      ~Rel() { fmm::release(t); }
+    } rel{h->t};
+    run_evaluation(h->t, s, [&] { fmm::evaluate(h->t, q, p, FMM_PART_ALL, FMM_PREC_F64, pot, ex, ey, ez, s); });
   });
 }
 
-int fmm_free(fmm_tree* tree) {
+fmm_status fmm_free(fmm_tree* tree) {
   return fmm::guarded([&] {
     if (!tree) return;
     fmm::release(tree->t);
@@ -344,7 +478,7 @@ int fmm_free(fmm_tree* tree) {
 
 const char* fmm_last_error(void) { return fmm::g_err.c_str(); }
 
-int fmm_tree_info(const fmm_tree* tree, int64_t* n, int* levels, double* theta) {
+fmm_status fmm_tree_info(const fmm_tree* tree, int64_t* n, int* levels, double* theta) {
   return fmm::guarded([&] {
     const fmm::Tree& t = get(tree);
     if (n) *n = t.n;
@@ -353,7 +487,7 @@ int fmm_tree_info(const fmm_tree* tree, int64_t* n, int* levels, double* theta) 
   });
 }
 
-int fmm_tree_perm(const fmm_tree* tree, int32_t* perm) {
+fmm_status fmm_tree_perm(const fmm_tree* tree, int32_t* perm) {
   return fmm::guarded([&] {
     const fmm::Tree& t = get(tree);
     if (!perm) fail(FMM_EINVAL, "perm is NULL");
@@ -362,7 +496,7 @@ int fmm_tree_perm(const fmm_tree* tree, int32_t* perm) {
   });
 }
 
-int fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start) {
+fmm_status fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start) {
   return fmm::guarded([&] {
     const fmm::Tree& t = get(tree);
     if (level < 0 || level > t.L) fail(FMM_EINVAL, "level out of range");
@@ -377,7 +511,7 @@ int fmm_tree_boxes(const fmm_tree* tree, int level, double* geom, int64_t* start
   });
 }
 
-int fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int64_t* offsets, int32_t* idx) {
+fmm_status fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int64_t* offsets, int32_t* idx) {
   return fmm::guarded([&] {
     const fmm::Tree& t = get(tree);
     if (level < 0 || level > t.L) fail(FMM_EINVAL, "level out of range");
@@ -394,7 +528,7 @@ int fmm_tree_lists(const fmm_tree* tree, int level, int kind, int64_t* nnz, int6
   });
 }
 
-int fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs) {
+fmm_status fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs) {
   return fmm::guarded([&] {
     const fmm::Tree& t = get(tree);
     if (m2l_pairs) *m2l_pairs = t.m2l_pairs;
@@ -402,12 +536,30 @@ int fmm_tree_stats(const fmm_tree* tree, int64_t* m2l_pairs, int64_t* p2p_pairs)
   });
 }
 
-int fmm_set_profiling(int on) {
+fmm_status fmm_set_allocator(fmm_alloc_fn alloc, fmm_free_fn free_fn, void* user) {
+  return fmm::guarded([&] {
+    if ((alloc == nullptr) != (free_fn == nullptr)) fail(FMM_EINVAL, "alloc and free must both be set or both NULL");
+    std::lock_guard<std::mutex> g(fmm::g_alloc_mu);
+    fmm::g_alloc = fmm::Allocator{alloc, free_fn, alloc ? user : nullptr};
+  });
+}
+
+fmm_status fmm_tree_bytes(const fmm_tree* tree, int p, int precision, size_t* tree_bytes, size_t* eval_bytes) {
+  return fmm::guarded([&] {
+    const fmm::Tree& t = get(tree);
+    if (p < 0 || p > FMM_MAX_ORDER) fail(FMM_EINVAL, "p must be in [0, 20]");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
+    if (tree_bytes) *tree_bytes = t.bytes;
+    if (eval_bytes) *eval_bytes = fmm::eval_scratch_bytes(t, p, precision);
+  });
+}
+
+fmm_status fmm_set_profiling(int on) {
   fmm::g_tm.on = on != 0;
   return FMM_OK;
 }
 
-int fmm_last_timings(double* ms) {
+fmm_status fmm_last_timings(double* ms) {
   return fmm::guarded([&] {
     if (!ms) fail(FMM_EINVAL, "ms is NULL");
     for (int k = 0; k < FMM_NUM_PHASES; ++k) {

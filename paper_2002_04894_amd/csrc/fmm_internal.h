@@ -27,9 +27,24 @@ struct Error {
 void check_hip(hipError_t e, const char* what);
 #define HIPCHECK(x) ::fmm::check_hip((x), #x)
 
-// Stream-ordered device allocation (pooled).
+// Device allocator: the hook set by fmm_set_allocator, or (all NULL) the
+// device's default stream-ordered pool.
+struct Allocator {
+  fmm_alloc_fn alloc = nullptr;
+  fmm_free_fn free = nullptr;
+  void* user = nullptr;
+};
+
+// Stream-ordered device allocation through the allocator of the current
+// entry-point call.  Every allocation is entered in the call's ledger until
+// it is freed, so that a call that fails frees what it allocated.
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
+
+// Per-thread pinned host words for small device-to-host read-backs (made
+// once per thread; kStageWords int64 values).
+constexpr int kStageWords = 64;
+int64_t* host_stage();
 
 // Per-level box geometry / lists in device memory.
 struct Level {
@@ -92,6 +107,12 @@ struct Tree {
   int32_t* tstart = nullptr;          // [nleaf + 1] target range of each leaf
   int64_t* p2p_leaf_tpart = nullptr;  // [nleaf + 1] first partial sum of each split leaf (targets)
   int64_t p2p_ntpart = 0;
+  // memory and stream bookkeeping (api.hip)
+  Allocator alloc;                 // allocator of the tree's own device memory
+  size_t bytes = 0;                // device bytes the tree owns
+  hipEvent_t built = nullptr;      // recorded on the build stream when the build is enqueued
+  hipStream_t build_stream = nullptr;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;  // last evaluation enqueued on each stream
   LevelView view() const;
 };
 
@@ -142,6 +163,10 @@ void evaluate_targets(const Tree& t, const double* q, int p, int parts, int prec
                       double* ez, hipStream_t s);
 void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey, double* ez,
               hipStream_t s);
+
+// peak scratch bytes of one evaluation (evaluate, plus evaluate_targets when
+// the tree has targets) at order p and precision prec
+size_t eval_scratch_bytes(const Tree& t, int p, int prec);
 
 // exclusive scan of int32 counts into int64 offsets (out[n] = total + base)
 void scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t base, hipStream_t s);

@@ -181,6 +181,17 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* 
 }  // namespace
 
 namespace {
+// level 0: the root is strongly connected to itself and to nothing else
+__global__ void k_root_lists(int64_t* __restrict__ s_off, int64_t* __restrict__ w_off, int32_t* __restrict__ s_idx) {
+  if (threadIdx.x == 0) {
+    s_off[0] = 0;
+    s_off[1] = 1;
+    w_off[0] = 0;
+    w_off[1] = 0;
+    s_idx[0] = 0;
+  }
+}
+
 template <class TIn>
 void scan_any(const TIn* in, int64_t* out, int64_t n, int64_t base, hipStream_t s) {
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
@@ -211,22 +222,16 @@ void lists_build(Tree& t, hipStream_t s) {
   // level 0: root strongly connected to itself
   {
     Level& V = t.lev[0];
-    const int64_t h_off[2] = {0, 1};
-    const int64_t h_woff[2] = {0, 0};
-    const int32_t h_idx[1] = {0};
     V.s_off = (int64_t*)dalloc(2 * sizeof(int64_t), s);
     V.w_off = (int64_t*)dalloc(2 * sizeof(int64_t), s);
     V.s_idx = (int32_t*)dalloc(sizeof(int32_t), s);
     V.w_idx = nullptr;
-    HIPCHECK(hipMemcpyAsync(V.s_off, h_off, sizeof(h_off), hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(V.w_off, h_woff, sizeof(h_woff), hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(V.s_idx, h_idx, sizeof(h_idx), hipMemcpyHostToDevice, s));
+    k_root_lists<<<1, 64, 0, s>>>(V.s_off, V.w_off, V.s_idx);
+    HIPCHECK(hipGetLastError());
     V.s_nnz = 1;
     V.w_nnz = 0;
-    HIPCHECK(hipStreamSynchronize(s));  // host sources above are on the stack
   }
-  int64_t* tot = nullptr;
-  HIPCHECK(hipHostMalloc((void**)&tot, 2 * sizeof(int64_t), hipHostMallocDefault));
+  int64_t* tot = host_stage();
   int64_t m2l = 0;
   for (int l = 1; l <= L; ++l) {
     Level& P = t.lev[l - 1];
@@ -256,7 +261,6 @@ void lists_build(Tree& t, hipStream_t s) {
     dfree(ns, s);
     dfree(nw, s);
   }
-  HIPCHECK(hipHostFree(tot));
   t.m2l_pairs = m2l;
 
   // M2L work order over the targets of levels 1..L (box id - 1)

@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "fmm_internal.h"
+#include "tile_layout.h"
 
 namespace fmm {
 
@@ -349,12 +350,10 @@ void p2p_plan_targets(Tree& t, hipStream_t s) {
   HIPCHECK(hipGetLastError());
   t.p2p_leaf_tpart = (int64_t*)dalloc((nleaf + 1) * sizeof(int64_t), s);
   scan_counts(pcnt, t.p2p_leaf_tpart, nleaf, 0, s);
-  int64_t* h = nullptr;
-  HIPCHECK(hipHostMalloc((void**)&h, sizeof(int64_t), hipHostMallocDefault));
+  int64_t* h = host_stage();
   HIPCHECK(hipMemcpyAsync(h, t.p2p_leaf_tpart + nleaf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   t.p2p_ntpart = *h;
-  HIPCHECK(hipHostFree(h));
   dfree(pcnt, s);
 }
 
@@ -377,8 +376,7 @@ void p2p_plan(Tree& t, hipStream_t s) {
   scan_counts(pcnt, t.p2p_leaf_part, nleaf, 0, s);
   k_sum64<<<(unsigned)((nleaf + 255) / 256), 256, 0, s>>>(nleaf, work, acc);
   HIPCHECK(hipGetLastError());
-  int64_t* h = nullptr;
-  HIPCHECK(hipHostMalloc((void**)&h, 3 * sizeof(int64_t), hipHostMallocDefault));
+  int64_t* h = host_stage();
   HIPCHECK(hipMemcpyAsync(&h[0], t.p2p_leaf_seg + nleaf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(&h[1], t.p2p_leaf_part + nleaf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(&h[2], acc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -386,7 +384,6 @@ void p2p_plan(Tree& t, hipStream_t s) {
   t.p2p_nseg = h[0];
   t.p2p_npart = h[1];
   t.p2p_pairs = h[2] - t.n;  // minus the n self pairs
-  HIPCHECK(hipHostFree(h));
   t.p2p_seg_leaf = (int32_t*)dalloc(std::max<int64_t>(1, t.p2p_nseg) * sizeof(int32_t), s);
   t.p2p_seg_e0 = (int64_t*)dalloc(std::max<int64_t>(1, t.p2p_nseg) * sizeof(int64_t), s);
   k_seg_plan<true><<<gw, 256, 0, s>>>(nleaf, V.start, V.s_off, V.s_idx, nullptr, nullptr, t.p2p_leaf_seg,
@@ -485,6 +482,27 @@ void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double
   for (int k = 0; k < 4; ++k)
     if (far[k]) dfree(far[k], s);
   dfree(qt, s);
+}
+
+size_t eval_scratch_bytes(const Tree& t, int p, int prec) {
+  // what evaluate() allocates, at its peak (far_field inside the charges'
+  // lifetime, then the near field's partial sums while the far field lives)
+  const size_t stride = p <= tl::kMaxP ? (size_t)tl::stride(p) : (size_t)nterms(p);
+  const size_t nbox = (size_t)t.nbox_total;
+  auto one = [&](int64_t npts, int64_t npart) {
+    const size_t qt = (size_t)t.n * 8;
+    const size_t far = t.L >= 1 ? 4 * (size_t)std::max<int64_t>(1, npts) * 8 : 0;
+    size_t expn = 0;
+    if (t.L >= 1) {
+      expn = 2 * nbox * stride * 8 + 256;                        // multipoles, locals, M2L queue
+      if (prec == FMM_PREC_MIXED && p <= tl::kMaxP) expn += nbox * stride * 4;  // binary32 multipoles
+    }
+    const size_t part = (size_t)std::max<int64_t>(0, npart) * 32;
+    return qt + far + std::max(expn, part);
+  };
+  size_t b = one(t.n, t.p2p_npart);
+  if (t.m > 0) b = std::max(b, one(t.m, t.p2p_ntpart));
+  return b;
 }
 
 // phi and E at the tree's separate targets (outputs in the caller's target

@@ -24,6 +24,11 @@ MAX_LEVELS, MAX_ORDER = 8, 20
 
 _lib = None
 
+# signatures of the allocator hook (fmm_set_allocator)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+_hook_refs = None  # keeps the ctypes callbacks of the current hook alive
+
 
 class FMMError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -60,10 +65,12 @@ def lib():
     L.fmm_last_timings.argtypes = [vp]
     L.fmm_bytes_estimate.argtypes = [i64, i32, d, i32]
     L.fmm_bytes_estimate.restype = C.c_size_t
+    L.fmm_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+    L.fmm_tree_bytes.argtypes = [vp, i32, i32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     for f in ("fmm_build", "fmm_build_ex", "fmm_evaluate_targets", "fmm_tree_targets", "fmm_evaluate_tree_ex",
               "fmm_evaluate_tree", "fmm_evaluate_tree_parts", "fmm_evaluate", "fmm_free",
               "fmm_tree_info", "fmm_tree_perm", "fmm_tree_boxes", "fmm_tree_lists", "fmm_tree_stats",
-              "fmm_set_profiling", "fmm_last_timings"):
+              "fmm_set_profiling", "fmm_last_timings", "fmm_set_allocator", "fmm_tree_bytes"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -116,7 +123,13 @@ class Tree:
             pass
 
 
+def _same_length(x, y, z, names=("x", "y", "z")):
+    if not (y.numel() == x.numel() and z.numel() == x.numel()):
+        raise ValueError(f"{', '.join(names)} must have the same length")
+
+
 def fmm_build(x, y, z, levels: int, theta: float, stream=None) -> Tree:
+    _same_length(x, y, z)
     for t, nm in ((x, "x"), (y, "y"), (z, "z")):
         _dev(t, nm)
     h = C.c_void_p()
@@ -127,6 +140,7 @@ def fmm_build(x, y, z, levels: int, theta: float, stream=None) -> Tree:
 
 def fmm_build_ex(x, y, z, levels: int, theta: float, eta: float = 1.0, targets=None, stream=None) -> Tree:
     """Tree with split parameter eta and optional separate targets (tx, ty, tz)."""
+    _same_length(x, y, z)
     for t, nm in ((x, "x"), (y, "y"), (z, "z")):
         _dev(t, nm)
     if targets is None:
@@ -186,6 +200,7 @@ def fmm_evaluate_tree(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts
 def fmm_evaluate(x, y, z, q, theta: float, p: int, levels: int, pot, ex, ey, ez, stream=None):
     for t, nm in ((x, "x"), (y, "y"), (z, "z"), (q, "q"), (pot, "pot"), (ex, "ex"), (ey, "ey"), (ez, "ez")):
         _dev(t, nm)
+    for t, nm in ((y, "y"), (z, "z"), (q, "q"), (pot, "pot"), (ex, "ex"), (ey, "ey"), (ez, "ez")):
         if t.numel() != x.numel():
             raise ValueError(f"{nm} must have {x.numel()} elements")
     _check(lib().fmm_evaluate(_ptr(x), _ptr(y), _ptr(z), _ptr(q), x.numel(), float(theta), int(p), int(levels),
@@ -243,6 +258,93 @@ def fmm_last_timings() -> dict:
     ms = np.zeros(len(PHASES))
     _check(lib().fmm_last_timings(ms.ctypes.data))
     return dict(zip(PHASES, ms.tolist()))
+
+
+def fmm_tree_bytes(tree: Tree, p: int, precision: int = FMM_PREC_F64):
+    """(device bytes the tree owns, peak scratch bytes of one evaluation)."""
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(lib().fmm_tree_bytes(tree.handle, int(p), int(precision), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def fmm_set_allocator(alloc=None, free=None):
+    """Routes the library's device allocations through Python callables
+    alloc(nbytes, stream) -> int pointer (0 on failure) and free(ptr, stream);
+    with no arguments the library's own stream-ordered pool is restored.
+    The callables are kept alive until the next call."""
+    global _hook_refs
+    if (alloc is None) != (free is None):
+        raise ValueError("alloc and free must both be given or both omitted")
+    if alloc is None:
+        _check(lib().fmm_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _hook_refs = None
+        return
+
+    def _a(nbytes, stream, user):
+        try:
+            return int(alloc(int(nbytes), stream or 0) or 0)
+        except Exception:
+            return 0
+
+    def _f(ptr, stream, user):
+        try:
+            free(int(ptr), stream or 0)
+        except Exception:
+            pass
+
+    refs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(lib().fmm_set_allocator(refs[0], refs[1], None))
+    _hook_refs = refs
+
+
+class TorchAllocator:
+    """Device memory from PyTorch's caching allocator, with an optional
+    budget in bytes: an allocation that would exceed it fails, and the
+    library then fails the call with FMM_ENOMEM (its allocations freed).
+    A block freed on another stream than the one it was allocated on is
+    handed back only after that stream's work is done."""
+
+    def __init__(self, budget: int | None = None):
+        import threading
+        import torch
+        self._torch = torch
+        self.budget = budget
+        self.in_use = 0
+        self.peak = 0
+        self.live = {}
+        self._mu = threading.Lock()
+
+    def alloc(self, nbytes: int, stream: int) -> int:
+        with self._mu:
+            if self.budget is not None and self.in_use + nbytes > self.budget:
+                return 0
+            self.in_use += nbytes
+            self.peak = max(self.peak, self.in_use)
+        try:
+            dev = self._torch.cuda.current_device()
+            ptr = int(self._torch.cuda.caching_allocator_alloc(nbytes, dev, stream))
+        except Exception:
+            with self._mu:
+                self.in_use -= nbytes
+            return 0
+        with self._mu:
+            self.live[ptr] = (nbytes, stream)
+        return ptr
+
+    def free(self, ptr: int, stream: int) -> None:
+        with self._mu:
+            nbytes, astream = self.live.pop(ptr)
+            self.in_use -= nbytes
+        if stream != astream:
+            if stream:
+                self._torch.cuda.ExternalStream(stream).synchronize()
+            else:
+                self._torch.cuda.synchronize()
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+    def install(self):
+        fmm_set_allocator(self.alloc, self.free)
+        return self
 
 
 def fmm_bytes_estimate(n: int, levels: int, theta: float, p: int) -> int:

@@ -93,3 +93,32 @@ def test_no_device_reports_edevice():
         pytest.skip("a device is present; valid-argument calls need real device pointers")
     rc, h = _build()
     assert rc == fmm.FMM_EDEVICE and "device" in fmm.fmm_last_error()
+
+
+def test_build_rejects_mismatched_lengths_before_the_library():
+    """x, y and z of different lengths are refused in the binding, before any
+    pointer reaches the library (a short y or z would be read past its end)."""
+    import torch
+    x = torch.zeros(10, dtype=torch.float64)
+    short = torch.zeros(9, dtype=torch.float64)
+    with pytest.raises(ValueError, match="same length"):
+        fmm.fmm_build(x, short, x, 2, 0.5)
+    with pytest.raises(ValueError, match="same length"):
+        fmm.fmm_build(x, x, short, 2, 0.5)
+    with pytest.raises(ValueError, match="same length"):
+        fmm.fmm_build_ex(x, short, x, 2, 0.5)
+
+
+def test_set_allocator_arguments():
+    L = fmm.lib()
+    assert L.fmm_set_allocator(fmm.ALLOC_FN(lambda n, s, u: 0), fmm.FREE_FN(), None) == fmm.FMM_EINVAL
+    assert "both" in fmm.fmm_last_error()
+    assert L.fmm_set_allocator(fmm.ALLOC_FN(), fmm.FREE_FN(lambda p, s, u: None), None) == fmm.FMM_EINVAL
+    fmm.fmm_set_allocator(lambda n, s: 0, lambda p, s: None)
+    fmm.fmm_set_allocator()  # back to the default pool
+    with pytest.raises(ValueError):
+        fmm.fmm_set_allocator(lambda n, s: 0)
+
+
+def test_tree_bytes_rejects_null_handle():
+    assert fmm.lib().fmm_tree_bytes(None, 5, 0, None, None) == fmm.FMM_EINVAL
