@@ -34,6 +34,12 @@
  *    Section 2.1.1: only children of strongly connected parents are tested.
  *  - Expansion order p = highest degree kept, (p+1)^2 complex terms.
  *  - M2L at every level 1..L, L2L for levels 1..L-1 (reading of Algorithm 3).
+ *  - M2L has two forms with the same result up to rounding: the basic
+ *    O(p^4) translation theorem (default) and the rotational O(p^3) form the
+ *    paper uses (Section 2.1.3), selected by orc_set_m2l_form.  The test-suite
+ *    pins each against the other.
+ *  - OpenMP threads share out independent boxes, leaves and targets only;
+ *    every sum runs in the same order as with one thread.
  *
  * Pins: the test-suite checks every function here against closed forms,
  * hand-derived golden trees and lists, exactness identities of the
@@ -45,6 +51,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -96,6 +103,7 @@ static double acc_get(const acc_t* a) { return a->s + a->c; }
 void orc_direct(int64_t n, const double* x, const double* y, const double* z, const double* q,
                 int64_t nt, const int64_t* targets, double* phi, double* ex, double* ey, double* ez) {
   if (targets == NULL) nt = n;
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < nt; ++k) {
     int64_t i = targets ? targets[k] : k;
     acc_t ap = {0, 0}, ax = {0, 0}, ay = {0, 0}, az = {0, 0};
@@ -220,6 +228,12 @@ static double Acoef(int n, int m) {
   return g_A[n][m];
 }
 
+/* Tables that are filled lazily; filled before any parallel region. */
+static void orc_init(void) {
+  init_fact();
+  (void)Acoef(0, 0);
+}
+
 /* i^e for any integer e */
 static cplx ipow(int e) {
   switch (((e % 4) + 4) % 4) {
@@ -304,6 +318,157 @@ void orc_m2l_add(int p, const cplx* O, double dx, double dy, double dz, cplx* L)
       }
       L[IDX(j, k)] += acc;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* M2L in rotational form (Section 2.1.3: the z-axis of the expansion is    */
+/* turned onto the vector between the two centres, O(p^3) per pair).        */
+/* ------------------------------------------------------------------------ */
+
+/* For a rotation R let D_n(R) be defined by Y_n^m(R u) = sum_m' D[m][m']
+ * Y_n^m'(u) for unit u.  Then D(R1 R2) = D(R1) D(R2), D(Rz(g)) = diag(e^{i m g}),
+ * and D is unitary (all Y_n^m have the same norm 4 pi / (2n+1) over the
+ * sphere).  Only D_n(K) for the fixed quarter turn K = Rx(-pi/2) (K z = y) is
+ * tabulated, by projection:
+ *   D[m][m'] = (2n+1)/(4 pi) * integral Y_n^m(K u) conj(Y_n^m'(u)) du,
+ * with a product rule exact for these integrands: Gauss-Legendre in cos(t)
+ * with n+1 nodes (exact to degree 2n+1) and 2n+1 equispaced azimuths (which
+ * cancel every azimuthal frequency 0 < |f| <= 2n). */
+static cplx* g_dk[ORC_PMAX + 1];
+
+/* P_k(t) and P_{k-1}(t) by the three-term Legendre recurrence */
+static void legendre_pair(int k, double t, double* pk, double* pkm1) {
+  double p0 = 1.0, p1 = t;
+  for (int j = 2; j <= k; ++j) {
+    const double p2 = ((2.0 * j - 1.0) * t * p1 - (j - 1.0) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  *pk = p1;
+  *pkm1 = p0;
+}
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (npts >= 1): Newton's method
+ * on P_npts from the usual cosine guesses; w = 2 / ((1 - t^2) P'(t)^2). */
+static void gauss_legendre_nodes(int npts, double* x, double* w) {
+  for (int i = 0; i < npts; ++i) {
+    double t = cos(M_PI * (i + 0.75) / (npts + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double pk, pm;
+      legendre_pair(npts, t, &pk, &pm);
+      const double dp = npts * (t * pk - pm) / (t * t - 1.0);
+      const double dt = pk / dp;
+      t -= dt;
+      if (fabs(dt) <= 1e-15 * fabs(t) + 1e-300) break;
+    }
+    double pk, pm;
+    legendre_pair(npts, t, &pk, &pm);
+    const double dp = npts * (t * pk - pm) / (t * t - 1.0);
+    x[i] = t;
+    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+static void rot_tables(int p) {
+  init_fact();
+  for (int n = 0; n <= p; ++n) {
+    if (g_dk[n]) continue;
+    const int w2 = 2 * n + 1;
+    cplx* D = (cplx*)xcalloc((size_t)w2 * w2, sizeof(cplx));
+    double xs[ORC_PMAX + 1], ws[ORC_PMAX + 1];
+    gauss_legendre_nodes(n + 1, xs, ws);
+    cplx Yu[NTERMS(ORC_PMAX)], Yk[NTERMS(ORC_PMAX)];
+    for (int i = 0; i <= n; ++i) {
+      const double ct = xs[i], st = sqrt(1.0 - ct * ct);
+      for (int k = 0; k < w2; ++k) {
+        const double ph = 2.0 * M_PI * k / w2;
+        const double ux = st * cos(ph), uy = st * sin(ph), uz = ct;
+        solid_harmonics(n, ux, uy, uz, Yu, NULL);
+        solid_harmonics(n, ux, uz, -uy, Yk, NULL); /* K u = (x, z, -y) */
+        const double wt = ws[i] * (2.0 * M_PI / w2) * (2.0 * n + 1.0) / (4.0 * M_PI);
+        for (int m = -n; m <= n; ++m)
+          for (int mp = -n; mp <= n; ++mp) D[(m + n) * w2 + (mp + n)] += wt * Yk[IDX(n, m)] * conj(Yu[IDX(n, mp)]);
+      }
+    }
+    g_dk[n] = D;
+  }
+}
+
+/* The same result as orc_m2l_add (up to rounding), computed by rotation.
+ * With d = rho (sin a cos b, sin a sin b, cos a) and Q = Rz(b) K Rz(a) K^-1
+ * (Q z = d/rho), the far field about the source centre, written in the frame
+ * x = Q x', has coefficients O' = D(Q)^T O per degree, i.e.
+ *   O' = conj(D(K)) Dz(a) D(K)^T Dz(b) O;
+ * along the z-axis the translation theorem keeps the order k:
+ *   L'_j^k = sum_{n >= |k|} O'_n^k (-1)^|k| A_n^k A_j^k / ((-1)^n A_{j+n}^0 rho^{j+n+1});
+ * and the local expansion returns to the original frame by the inverse of
+ * D(Q)^T, which is conj(D(Q)):
+ *   L = Dz(-b) conj(D(K)) Dz(-a) D(K)^T L'.
+ * d = source centre - target centre.  The result is added to L.  The tables
+ * of order p must exist (orc_rot_prepare) before parallel use. */
+void orc_m2l_rot_add(int p, const cplx* O, double dx, double dy, double dz, cplx* L) {
+  rot_tables(p);
+  const double rxy = sqrt(dx * dx + dy * dy);
+  const double rho = sqrt(dx * dx + dy * dy + dz * dz);
+  const double a = atan2(rxy, dz), b = atan2(dy, dx);
+  cplx Op[NTERMS(ORC_PMAX)], Lp[NTERMS(ORC_PMAX)];
+  cplx w[2 * ORC_PMAX + 1], v[2 * ORC_PMAX + 1];
+  for (int n = 0; n <= p; ++n) {
+    const cplx* D = g_dk[n];
+    const int w2 = 2 * n + 1;
+    for (int m = -n; m <= n; ++m) w[m + n] = cexp(I * (double)m * b) * O[IDX(n, m)];
+    for (int mp = -n; mp <= n; ++mp) {
+      cplx acc = 0.0;
+      for (int m = -n; m <= n; ++m) acc += D[(m + n) * w2 + (mp + n)] * w[m + n];
+      v[mp + n] = cexp(I * (double)mp * a) * acc;
+    }
+    for (int m = -n; m <= n; ++m) {
+      cplx acc = 0.0;
+      for (int q = -n; q <= n; ++q) acc += conj(D[(m + n) * w2 + (q + n)]) * v[q + n];
+      Op[IDX(n, m)] = acc;
+    }
+  }
+  for (int j = 0; j <= p; ++j)
+    for (int k = -j; k <= j; ++k) {
+      const int ak = abs(k);
+      cplx acc = 0.0;
+      for (int n = ak; n <= p; ++n) {
+        const double sgn = (((n + ak) & 1) ? -1.0 : 1.0);
+        acc += Op[IDX(n, k)] * (sgn * Acoef(n, ak) * Acoef(j, ak) / (Acoef(j + n, 0) * pow(rho, (double)(j + n + 1))));
+      }
+      Lp[IDX(j, k)] = acc;
+    }
+  for (int j = 0; j <= p; ++j) {
+    const cplx* D = g_dk[j];
+    const int w2 = 2 * j + 1;
+    for (int mp = -j; mp <= j; ++mp) {
+      cplx acc = 0.0;
+      for (int m = -j; m <= j; ++m) acc += D[(m + j) * w2 + (mp + j)] * Lp[IDX(j, m)];
+      w[mp + j] = cexp(-I * (double)mp * a) * acc;
+    }
+    for (int m = -j; m <= j; ++m) {
+      cplx acc = 0.0;
+      for (int q = -j; q <= j; ++q) acc += conj(D[(m + j) * w2 + (q + j)]) * w[q + j];
+      L[IDX(j, m)] += cexp(-I * (double)m * b) * acc;
+    }
+  }
+}
+
+/* Which M2L form the whole-method evaluation uses: 0 = the basic O(p^4)
+ * translation theorem (default), 1 = the rotational form. */
+static int g_m2l_rot = 0;
+void orc_set_m2l_form(int rotational) { g_m2l_rot = rotational != 0; }
+/* Threads of the parallel loops (0 or less: the OpenMP default); returns the
+ * number the next parallel region will use. */
+int orc_set_threads(int nthreads) {
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+}
+void orc_rot_prepare(int p) { orc_init(); rot_tables(p); }
+
+static void m2l_add(int p, const cplx* O, double dx, double dy, double dz, cplx* L) {
+  if (g_m2l_rot) orc_m2l_rot_add(p, O, dx, dy, dz, L);
+  else orc_m2l_add(p, O, dx, dy, dz, L);
 }
 
 /* L2L: local expansion O about an old centre at (rho, alpha, beta) relative to
@@ -411,6 +576,7 @@ typedef struct {
   const double *tx, *ty, *tz;
   int32_t* perm;           /* tree order -> original index */
   orc_level* lev;          /* levels 0..L */
+  char* listed;            /* targeted mode: leaves whose chains have lists (NULL: all) */
 } orc_tree;
 
 typedef struct { double key; int32_t idx; } kv_t;
@@ -532,7 +698,14 @@ static void build_tree(orc_tree* t) {
   for (int l = 0; l < L; ++l) {
     orc_level* P = &t->lev[l];
     orc_level* C = &t->lev[l + 1];
+    /* boxes are independent: each works on its own range of perm and of the
+     * buffers kv, tmp, scratch */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t b = 0; b < P->nbox; ++b) {
+      const int64_t base = P->start[b];
+      kv_t* kvb = kv + base;
+      int32_t* tmpb = tmp + base;
+      int32_t* scrb = scratch + base;
       /* three successive bisections; sub-cells indexed by the bits so far */
       double clo[8][3], chi[8][3];
       int64_t cs[8], ce[8];
@@ -546,7 +719,7 @@ static void build_tree(orc_tree* t) {
         for (int c = 0; c < cnt; ++c) {
           int axis;
           double plane;
-          const int64_t m = bisect(t, t->perm, cs[c], ce[c], clo[c], chi[c], &axis, &plane, kv, tmp, scratch);
+          const int64_t m = bisect(t, t->perm, cs[c], ce[c], clo[c], chi[c], &axis, &plane, kvb, tmpb, scrb);
           for (int h = 0; h < 2; ++h) {
             const int o = 2 * c + h;
             memcpy(nlo[o], clo[c], sizeof(nlo[o]));
@@ -603,8 +776,10 @@ static int is_weak(const double* gi, const double* gj, double theta) {
 
 /* Connectivity per level (Section 2.1.1 inheritance; Algorithm 2): the
  * candidates of box i are the children of every box strongly connected to
- * the parent of i, in ascending order. */
-static void build_lists(orc_tree* t) {
+ * the parent of i, in ascending order.  need[l][i] = 0 leaves the rows of box
+ * i empty (targeted mode: only the ancestors of chosen leaves get lists; a
+ * needed box always has a needed parent); need == NULL builds every row. */
+static void build_lists_masked(orc_tree* t, char* const* need) {
   orc_level* V0 = &t->lev[0];
   V0->s_off = (int64_t*)xmalloc(2 * sizeof(int64_t));
   V0->s_idx = (int32_t*)xmalloc(sizeof(int32_t));
@@ -616,16 +791,46 @@ static void build_lists(orc_tree* t) {
   for (int l = 1; l <= t->L; ++l) {
     orc_level* P = &t->lev[l - 1];
     orc_level* V = &t->lev[l];
-    int64_t cap = 8 * P->s_off[P->nbox] * 8 + 1;
+    const char* nd = need ? need[l] : NULL;
+    int64_t* cs = (int64_t*)xcalloc((size_t)V->nbox + 1, sizeof(int64_t));
+    int64_t* cw = (int64_t*)xcalloc((size_t)V->nbox + 1, sizeof(int64_t));
+    /* count, then fill: the same candidate loop twice */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < V->nbox; ++i) {
+      if (nd && !nd[i]) continue;
+      const int64_t par = i / 8;
+      int64_t ns = 0, nw = 0;
+      for (int64_t e = P->s_off[par]; e < P->s_off[par + 1]; ++e) {
+        const int64_t J = P->s_idx[e];
+        for (int c = 0; c < 8; ++c) {
+          const int64_t j = 8 * J + c;
+          if (j != i && is_weak(V->geom + i * 10, V->geom + j * 10, t->theta)) ++nw;
+          else ++ns;
+        }
+      }
+      cs[i] = ns;
+      cw[i] = nw;
+    }
     V->s_off = (int64_t*)xmalloc((size_t)(V->nbox + 1) * sizeof(int64_t));
     V->w_off = (int64_t*)xmalloc((size_t)(V->nbox + 1) * sizeof(int64_t));
-    V->s_idx = (int32_t*)xmalloc((size_t)cap * sizeof(int32_t));
-    V->w_idx = (int32_t*)xmalloc((size_t)cap * sizeof(int32_t));
-    int64_t ns = 0, nw = 0;
+    int64_t ts = 0, tw = 0;
     for (int64_t i = 0; i < V->nbox; ++i) {
-      V->s_off[i] = ns;
-      V->w_off[i] = nw;
+      V->s_off[i] = ts;
+      V->w_off[i] = tw;
+      ts += cs[i];
+      tw += cw[i];
+    }
+    V->s_off[V->nbox] = ts;
+    V->w_off[V->nbox] = tw;
+    free(cs);
+    free(cw);
+    V->s_idx = (int32_t*)xmalloc((size_t)(ts > 0 ? ts : 1) * sizeof(int32_t));
+    V->w_idx = (int32_t*)xmalloc((size_t)(tw > 0 ? tw : 1) * sizeof(int32_t));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < V->nbox; ++i) {
+      if (nd && !nd[i]) continue;
       const int64_t par = i / 8;
+      int64_t ns = V->s_off[i], nw = V->w_off[i];
       for (int64_t e = P->s_off[par]; e < P->s_off[par + 1]; ++e) {
         const int64_t J = P->s_idx[e];
         for (int c = 0; c < 8; ++c) {
@@ -635,10 +840,10 @@ static void build_lists(orc_tree* t) {
         }
       }
     }
-    V->s_off[V->nbox] = ns;
-    V->w_off[V->nbox] = nw;
   }
 }
+
+static void build_lists(orc_tree* t) { build_lists_masked(t, NULL); }
 
 /* ------------------------------------------------------------------------ */
 /* Public tree API                                                          */
@@ -648,6 +853,7 @@ static void build_lists(orc_tree* t) {
  * root cell so that every target lies in some leaf cell.  eta as in bisect. */
 void* orc_create_ex(int64_t n, const double* x, const double* y, const double* z, int64_t m, const double* tx,
                     const double* ty, const double* tz, int L, double theta, double eta) {
+  orc_init();
   orc_tree* t = (orc_tree*)xcalloc(1, sizeof(orc_tree));
   t->n = n;
   t->L = L;
@@ -665,6 +871,67 @@ void* orc_create_ex(int64_t n, const double* x, const double* y, const double* z
   return t;
 }
 
+/* Targeted mode, for trees whose full lists do not fit in host memory: the
+ * tree is built in full, but the strong and weak lists only for the
+ * ancestors of the nleaves listed leaves (every other row is empty).  The
+ * tree can then be evaluated at (a subset of) those leaves only: the
+ * upward pass is complete, M2L and L2L run along the chains of the listed
+ * leaves, P2P over their strong lists -- the same arithmetic as a full tree
+ * evaluated at those leaves. */
+void* orc_create_targeted(int64_t n, const double* x, const double* y, const double* z, int L, double theta,
+                          int64_t nleaves, const int64_t* leaves) {
+  orc_init();
+  orc_tree* t = (orc_tree*)xcalloc(1, sizeof(orc_tree));
+  t->n = n;
+  t->L = L;
+  t->theta = theta;
+  t->eta = 1.0;
+  t->x = x;
+  t->y = y;
+  t->z = z;
+  build_tree(t);
+  char** need = (char**)xcalloc((size_t)L + 1, sizeof(char*));
+  for (int l = 0; l <= L; ++l) need[l] = (char*)xcalloc((size_t)t->lev[l].nbox, 1);
+  for (int64_t s = 0; s < nleaves; ++s) {
+    int64_t b = leaves[s];
+    for (int l = L; l >= 0; --l, b /= 8) need[l][b] = 1;
+  }
+  build_lists_masked(t, need);
+  t->listed = need[L];
+  for (int l = 0; l < L; ++l) free(need[l]);
+  free(need);
+  return t;
+}
+
+/* Rebuilds the lists of a tree for another theta (the tree does not depend
+ * on theta); a targeted tree keeps its chosen leaves. */
+void orc_set_theta(void* h, double theta) {
+  orc_tree* t = (orc_tree*)h;
+  for (int l = 0; l <= t->L; ++l) {
+    orc_level* V = &t->lev[l];
+    free(V->s_off); free(V->s_idx); free(V->w_off); free(V->w_idx);
+    V->s_off = V->w_off = NULL;
+    V->s_idx = V->w_idx = NULL;
+  }
+  t->theta = theta;
+  if (!t->listed) {
+    build_lists(t);
+    return;
+  }
+  const int L = t->L;
+  char** need = (char**)xcalloc((size_t)L + 1, sizeof(char*));
+  for (int l = 0; l < L; ++l) need[l] = (char*)xcalloc((size_t)t->lev[l].nbox, 1);
+  need[L] = t->listed;
+  for (int64_t b = 0; b < t->lev[L].nbox; ++b) {
+    if (!t->listed[b]) continue;
+    int64_t a = b / 8;
+    for (int l = L - 1; l >= 0; --l, a /= 8) need[l][a] = 1;
+  }
+  build_lists_masked(t, need);
+  for (int l = 0; l < L; ++l) free(need[l]);
+  free(need);
+}
+
 void* orc_create(int64_t n, const double* x, const double* y, const double* z, int L, double theta) {
   return orc_create_ex(n, x, y, z, 0, NULL, NULL, NULL, L, theta, 1.0);
 }
@@ -678,6 +945,7 @@ void orc_destroy(void* h) {
   }
   free(t->lev);
   free(t->perm);
+  free(t->listed);
   free(t);
 }
 
@@ -741,23 +1009,27 @@ static cplx** far_pass(const orc_tree* t, const double* px, const double* py, co
 
   cplx** Mx = (cplx**)xcalloc((size_t)L + 1, sizeof(cplx*));
   cplx** Lx = (cplx**)xcalloc((size_t)L + 1, sizeof(cplx*));
+  orc_init();
+  if (g_m2l_rot) rot_tables(p);
   {
     for (int l = 1; l <= L; ++l) {
       Mx[l] = (cplx*)xcalloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
       Lx[l] = (cplx*)xcalloc((size_t)t->lev[l].nbox * nt, sizeof(cplx));
     }
     /* P2M on level L */
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t b = 0; b < leaf->nbox; ++b) {
       const double* g = leaf->geom + b * 10;
       const int64_t s = leaf->start[b], e = leaf->start[b + 1];
       orc_p2m(p, g[6], g[7], g[8], e - s, px + s, py + s, pz + s, pq + s, Mx[L] + b * nt);
     }
     /* M2M, l = L .. 2: parents on level l-1 from their 8 children */
-    cplx tmpM[NTERMS(ORC_PMAX)];
     for (int l = L; l >= 2; --l) {
       const orc_level* C = &t->lev[l];
       const orc_level* P = &t->lev[l - 1];
+#pragma omp parallel for schedule(dynamic, 64)
       for (int64_t b = 0; b < P->nbox; ++b) {
+        cplx tmpM[NTERMS(ORC_PMAX)];
         const double* gp = P->geom + b * 10;
         cplx* dst = Mx[l - 1] + b * nt;
         for (int c = 0; c < 8; ++c) {
@@ -771,6 +1043,7 @@ static cplx** far_pass(const orc_tree* t, const double* px, const double* py, co
     /* downward pass over the needed boxes: M2L at every level, then L2L */
     for (int l = 1; l <= L; ++l) {
       const orc_level* V = &t->lev[l];
+#pragma omp parallel for schedule(dynamic, 1)
       for (int64_t i = 0; i < V->nbox; ++i) {
         if (!need[l][i]) continue;
         cplx* dst = Lx[l] + i * nt;
@@ -785,7 +1058,7 @@ static cplx** far_pass(const orc_tree* t, const double* px, const double* py, co
         for (int64_t e = V->w_off[i]; e < V->w_off[i + 1]; ++e) {
           const int64_t j = V->w_idx[e];
           const double* gj = V->geom + j * 10;
-          orc_m2l_add(p, Mx[l] + j * nt, gj[6] - gi[6], gj[7] - gi[7], gj[8] - gi[8], dst);
+          m2l_add(p, Mx[l] + j * nt, gj[6] - gi[6], gj[7] - gi[7], gj[8] - gi[8], dst);
         }
       }
     }
@@ -809,6 +1082,9 @@ int orc_evaluate(void* h, const double* q, int p, int parts, int64_t nleaves, co
   const int nt = NTERMS(p);
   const orc_level* leaf = &t->lev[L];
   if (leaves == NULL) nleaves = leaf->nbox;
+  if (t->listed) /* targeted mode: only leaves whose chains have lists */
+    for (int64_t s = 0; s < nleaves; ++s)
+      if (!leaves || !t->listed[leaves[s]]) return -3;
 
   /* point data in tree order */
   const int64_t n = t->n;
@@ -827,6 +1103,7 @@ int orc_evaluate(void* h, const double* q, int p, int parts, int64_t nleaves, co
   cplx** Lx = ((parts & 2) && L >= 1) ? far_pass(t, px, py, pz, pq, p, need_leaf) : NULL;
   free(need_leaf);
 
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t s = 0; s < nleaves; ++s) {
     const int64_t b = leaves ? leaves[s] : s;
     const double* g = leaf->geom + b * 10;
@@ -907,6 +1184,7 @@ int orc_evaluate_targets(void* h, const double* q, int p, int parts, double* phi
                          double* ez) {
   orc_tree* t = (orc_tree*)h;
   if (p < 0 || p > ORC_PMAX) return -1;
+  if (t->listed) return -3;
   const int L = t->L;
   const int nt = NTERMS(p);
   const orc_level* leaf = &t->lev[L];
@@ -929,6 +1207,7 @@ int orc_evaluate_targets(void* h, const double* q, int p, int parts, double* phi
   cplx** Lx = ((parts & 2) && L >= 1) ? far_pass(t, px, py, pz, pq, p, need_leaf) : NULL;
   free(need_leaf);
 
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < m; ++k) {
     const int64_t b = tleaf[k];
     const double x = t->tx[k] + 0.0, y = t->ty[k] + 0.0, z = t->tz[k] + 0.0;

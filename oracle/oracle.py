@@ -11,7 +11,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-__all__ = ["build", "direct", "Tree", "p2m", "m2m", "m2l", "l2l", "l2p", "m2p", "p2l", "nterms", "idx"]
+__all__ = ["build", "direct", "Tree", "p2m", "m2m", "m2l", "m2l_rot", "set_m2l_form", "set_threads", "l2l", "l2p", "m2p", "p2l",
+           "nterms", "idx"]
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _cp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
@@ -54,6 +55,14 @@ def _load():
     lib.orc_p2m.argtypes = [i32, d, d, d, i64, _dp, _dp, _dp, _dp, _cp]
     lib.orc_m2m.argtypes = [i32, _cp, d, d, d, _cp]
     lib.orc_m2l_add.argtypes = [i32, _cp, d, d, d, _cp]
+    lib.orc_m2l_rot_add.argtypes = [i32, _cp, d, d, d, _cp]
+    lib.orc_set_m2l_form.argtypes = [i32]
+    lib.orc_rot_prepare.argtypes = [i32]
+    lib.orc_set_threads.argtypes = [i32]
+    lib.orc_set_threads.restype = i32
+    lib.orc_create_targeted.argtypes = [i64, _dp, _dp, _dp, i32, d, i64, _i64p]
+    lib.orc_create_targeted.restype = C.c_void_p
+    lib.orc_set_theta.argtypes = [C.c_void_p, d]
     lib.orc_l2l_add.argtypes = [i32, _cp, d, d, d, _cp]
     lib.orc_l2p_add.argtypes = [i32, _cp, d, d, d, d, d, d] + [C.POINTER(C.c_double)] * 4
     lib.orc_m2p.argtypes = [i32, _cp, d, d, d, d, d, d, C.POINTER(C.c_double)]
@@ -94,15 +103,27 @@ def direct(x, y, z, q, targets=None):
 class Tree:
     """ORB tree + theta-criterion lists + FMM evaluation (all on the CPU)."""
 
-    def __init__(self, x, y, z, levels: int, theta: float, eta: float = 1.0, targets=None):
+    def __init__(self, x, y, z, levels: int, theta: float, eta: float = 1.0, targets=None, leaves=None):
         """targets: optional (tx, ty, tz) of separate evaluation points; they
-        widen the root cell (see orc_create_ex).  eta: split parameter."""
+        widen the root cell (see orc_create_ex).  eta: split parameter.
+        leaves: targeted mode (orc_create_targeted): lists only along the
+        chains of these leaves, which are then the only ones that can be
+        evaluated (for trees whose full lists exceed host memory)."""
         lib = _load()
         self._x, self._y, self._z = map(_f64, (x, y, z))
         self.n = self._x.shape[0]
         self.levels = int(levels)
         self.theta = float(theta)
         self.eta = float(eta)
+        if leaves is not None:
+            if targets is not None or eta != 1.0:
+                raise ValueError("targeted mode takes neither targets nor eta")
+            self._t = None
+            self.m = 0
+            lv = np.ascontiguousarray(leaves, dtype=np.int64)
+            self._h = lib.orc_create_targeted(self.n, self._x, self._y, self._z, self.levels, self.theta,
+                                              lv.shape[0], lv)
+            return
         if targets is None:
             self._t = None
             self.m = 0
@@ -113,6 +134,12 @@ class Tree:
             ptrs = tuple(a.ctypes.data_as(C.c_void_p) for a in self._t)
         self._h = lib.orc_create_ex(self.n, self._x, self._y, self._z, self.m, *ptrs, self.levels, self.theta,
                                     self.eta)
+
+    def set_theta(self, theta: float) -> None:
+        """Rebuild the lists for another theta (same tree; a targeted tree
+        keeps its leaves)."""
+        _load().orc_set_theta(self._h, float(theta))
+        self.theta = float(theta)
 
     def close(self):
         if self._h:
@@ -202,6 +229,24 @@ def m2l(p, O, d):
     L = np.zeros(nterms(p), dtype=np.complex128)
     _load().orc_m2l_add(p, np.ascontiguousarray(O, dtype=np.complex128), *map(float, d), L)
     return L
+
+
+def m2l_rot(p, O, d):
+    """The rotational form of m2l (Section 2.1.3); d = source - target centre."""
+    L = np.zeros(nterms(p), dtype=np.complex128)
+    _load().orc_m2l_rot_add(p, np.ascontiguousarray(O, dtype=np.complex128), *map(float, d), L)
+    return L
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops (n <= 0: keep); returns the count in use."""
+    return int(_load().orc_set_threads(int(n)))
+
+
+def set_m2l_form(rotational: bool) -> None:
+    """M2L form of the whole-method evaluation: rotational (True) or the
+    basic translation theorem (False, the default)."""
+    _load().orc_set_m2l_form(1 if rotational else 0)
 
 
 def l2l(p, O, d):

@@ -4,10 +4,16 @@ A request carries a point cloud with charges and a requested relative
 accuracy.  The server admits requests in arrival order as soon as a worker is
 free and the device-memory estimate of the request (`fmm_bytes_estimate`)
 fits in the budget next to the requests already on the device: continuous
-batching, not a queue drained one at a time.  Every worker owns a HIP stream,
-so the solves of different requests overlap on the GPU.  Each request's
-result depends only on its own data and parameters (the solver is
-deterministic), so it is the same alone and in the mix.
+batching, not a queue drained one at a time.  Once a request's tree is built
+its reservation is replaced by the exact bytes (`fmm_tree_bytes`: the tree
+plus the evaluation's scratch), which on clustered clouds can exceed the
+estimate.  With `hard_budget` the library's device allocations go through a
+budgeted allocator as well (`fmm.TorchAllocator`): an allocation beyond the
+budget fails the solve with FMM_ENOMEM, its memory is given back, and the
+request waits for running requests to finish and runs again.  Every worker
+owns a HIP stream, so the solves of different requests overlap on the GPU.
+Each request's result depends only on its own data and parameters (the
+solver is deterministic), so it is the same alone and in the mix.
 
 The tuner picks (levels, theta, p, precision) per request:
   * levels: about kPointsPerLeaf points per leaf (8^levels leaves), a priori;
@@ -54,6 +60,9 @@ class Result:
     done: float = 0.0
     params: tuple = ()
     bytes_est: int = 0
+    bytes_exact: int = 0
+    retries: int = 0
+    dev_ms: tuple = ()  # device start and end of the solve (ms after the run's reference event)
     outputs: list = field(default_factory=list)  # phi, ex, ey, ez (host), when kept
     error: str = ""
 
@@ -254,26 +263,45 @@ class Tuner:
 class Server:
     """Continuous-batching server over `workers` HIP streams."""
 
-    def __init__(self, tuner: Tuner, workers: int = 6, hbm_budget: int = 64 << 30, keep_outputs: bool = False):
+    def __init__(self, tuner: Tuner, workers: int = 6, hbm_budget: int = 64 << 30, keep_outputs: bool = False,
+                 hard_budget: bool = False):
         self.tuner = tuner
         self.workers = workers
         self.budget = hbm_budget
         self.keep = keep_outputs
+        self.hard = hard_budget
         self._cv = threading.Condition()
         self._in_flight = 0
         self.peak_bytes = 0
         self.peak_concurrency = 0
+        self.deferred = 0   # admissions that had to wait for memory
+        self.retried = 0    # solves that failed on the hard budget and ran again
         self._active = 0
+        self._alloc = None
+        self._ref_event = None
 
-    # admission: wait until the request's estimate fits next to those running
+    # admission: wait until the request's reservation fits next to those running
     def _admit(self, nbytes: int):
         with self._cv:
+            waited = False
             while self._in_flight > 0 and self._in_flight + nbytes > self.budget:
+                waited = True
                 self._cv.wait()
+            if waited:
+                self.deferred += 1
             self._in_flight += nbytes
             self._active += 1
             self.peak_bytes = max(self.peak_bytes, self._in_flight)
             self.peak_concurrency = max(self.peak_concurrency, self._active)
+
+    # the reservation of a running request becomes its exact figure (no wait:
+    # the memory is already in use; later admissions see the new total)
+    def _resize(self, old: int, new: int):
+        with self._cv:
+            self._in_flight += new - old
+            self.peak_bytes = max(self.peak_bytes, self._in_flight)
+            if new < old:
+                self._cv.notify_all()
 
     def _release(self, nbytes: int):
         with self._cv:
@@ -281,22 +309,36 @@ class Server:
             self._active -= 1
             self._cv.notify_all()
 
-    def solve(self, req: Request, data, stream) -> Result:
-        """One request on `stream` (host data in, host results out)."""
+    def solve(self, req: Request, data, stream, reserve=None) -> Result:
+        """One request on `stream` (host data in, host results out).
+        reserve(tree, params) -> None is called once the tree is built."""
         import torch
         res = Result(req.rid, req.arrival)
         lev, theta, p, prec = self.tuner.choose(req.n, req.tol)
         res.params = (lev, theta, p, prec)
         x, y, z, q = data
         with torch.cuda.stream(stream):
-            dev = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda", non_blocking=False) for a in (x, y, z, q)]
+            host_in = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (x, y, z, q)]
+            dev = [h.to("cuda", non_blocking=True) for h in host_in]
             outs = [torch.empty_like(dev[0]) for _ in range(4)]
+            e0 = e1 = None
+            if self._ref_event is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
             tree = fmm.fmm_build(*dev[:3], lev, theta, stream)
             try:
+                tb, eb = fmm.fmm_tree_bytes(tree, p, prec)
+                res.bytes_exact = tb + eb + 8 * 8 * req.n
+                if reserve is not None:
+                    reserve(res.bytes_exact)
                 fmm.fmm_evaluate_tree(tree, dev[3], p, *outs, stream, precision=prec)
             finally:
                 tree.free()
+            if e1 is not None:
+                e1.record(stream)
             host = [o.cpu() for o in outs]  # waits for this stream's work
+            if e1 is not None:
+                res.dev_ms = (self._ref_event.elapsed_time(e0), self._ref_event.elapsed_time(e1))
         if self.keep:
             res.outputs = [h.numpy() for h in host]
         return res
@@ -310,6 +352,10 @@ class Server:
         results: list[Result] = []
         lock = threading.Lock()
         t0 = [0.0]
+        if self.hard:
+            self._alloc = fmm.TorchAllocator(budget=self.budget).install()
+        self._ref_event = torch.cuda.Event(enable_timing=True)
+        self._ref_event.record()
 
         def producer():
             # draws each request's data just before it arrives
@@ -332,17 +378,40 @@ class Server:
                 r, data = item
                 lev, th, p, _ = self.tuner.choose(r.n, r.tol)
                 est = int(fmm.fmm_bytes_estimate(r.n, lev, th, p))
-                self._admit(est)
-                start = time.perf_counter() - t0[0]
-                try:
-                    res = self.solve(r, data, stream)
-                except Exception as exc:  # reported per request
-                    res = Result(r.rid, r.arrival, error=str(exc))
-                finally:
-                    self._release(est)
+                start = None
+                retries = 0
+                while True:
+                    self._admit(est)
+                    held = [est]
+
+                    def reserve(nbytes, held=held):
+                        self._resize(held[0], nbytes)
+                        held[0] = nbytes
+
+                    if start is None:
+                        start = time.perf_counter() - t0[0]
+                    try:
+                        res = self.solve(r, data, stream, reserve)
+                    except fmm.FMMError as exc:
+                        res = Result(r.rid, r.arrival, error=str(exc))
+                        if exc.code == fmm.FMM_ENOMEM and self.hard and retries < 100:
+                            # over the hard budget: wait until the others are done
+                            # (the reservation becomes the whole budget) and run again
+                            self._resize(held[0], self.budget)
+                            held[0] = self.budget
+                            retries += 1
+                            with self._cv:
+                                self.retried += 1
+                            self._release(held[0])
+                            continue
+                    except Exception as exc:  # reported per request
+                        res = Result(r.rid, r.arrival, error=str(exc))
+                    self._release(held[0])
+                    break
                 res.start = start
                 res.done = time.perf_counter() - t0[0]
                 res.bytes_est = est
+                res.retries = retries
                 if not realtime:
                     res.arrival = 0.0
                 with lock:
@@ -351,11 +420,42 @@ class Server:
         t0[0] = time.perf_counter()
         threads = [threading.Thread(target=producer, daemon=True)]
         threads += [threading.Thread(target=worker, daemon=True) for _ in range(self.workers)]
-        for th in threads:
-            th.start()
-        for th in threads:
-            th.join()
+        try:
+            for th in threads:
+                th.start()
+            for th in threads:
+                th.join()
+        finally:
+            if self.hard:
+                torch.cuda.synchronize()
+                fmm.fmm_set_allocator()
         return sorted(results, key=lambda r: r.rid)
+
+
+def device_overlap(results: list[Result]) -> dict:
+    """From the device start/end of every solve: the time with at least one
+    solve on the device, and the share of it with two or more at once."""
+    ev = []
+    for r in results:
+        if r.dev_ms:
+            ev.append((r.dev_ms[0], 1))
+            ev.append((r.dev_ms[1], -1))
+    if not ev:
+        return {"busy_ms": 0.0, "overlap_frac": 0.0, "max_concurrent": 0}
+    ev.sort()
+    busy = over = 0.0
+    k = kmax = 0
+    last = ev[0][0]
+    for t, d in ev:
+        if k >= 1:
+            busy += t - last
+        if k >= 2:
+            over += t - last
+        k += d
+        kmax = max(kmax, k)
+        last = t
+    return {"busy_ms": round(busy, 3), "overlap_frac": round(over / busy, 4) if busy > 0 else 0.0,
+            "max_concurrent": kmax}
 
 
 def summary(results: list[Result], requests: list[Request]) -> dict:
@@ -374,11 +474,12 @@ def summary(results: list[Result], requests: list[Request]) -> dict:
         "makespan_s": round(span, 3),
         "requests_per_s": round(len(ok) / span, 2) if span > 0 else None,
         "points_per_s": round(pts / span, 1) if span > 0 else None,
+        "device_overlap": device_overlap(ok),
     }
 
 
 def run_stream(nreq: int = 4000, rate: float = 200.0, workers: int = 6, check_every: int = 500,
-               hbm_budget: int = 64 << 30) -> dict:
+               hbm_budget: int = 64 << 30, hard_budget: bool = False) -> dict:
     """Calibrate the tuner, serve the request stream in real time, and check
     every `check_every`-th result against the direct sum (`direct_sum`,
     binary64): p50/p99 latency, throughput and the accuracy checks."""
@@ -388,11 +489,14 @@ def run_stream(nreq: int = 4000, rate: float = 200.0, workers: int = 6, check_ev
     tuner.calibrate()
     cal_s = time.perf_counter() - t0
     reqs = make_stream(nreq, rate)
-    srv = Server(tuner, workers=workers, hbm_budget=hbm_budget)
+    srv = Server(tuner, workers=workers, hbm_budget=hbm_budget, hard_budget=hard_budget)
     results = srv.run(reqs, realtime=True)
     out = summary(results, reqs)
     out.update({"workers": workers, "hbm_budget_gb": round(hbm_budget / 2 ** 30, 1),
                 "peak_concurrency": srv.peak_concurrency, "peak_bytes_gb": round(srv.peak_bytes / 1e9, 3),
+                "deferred": srv.deferred, "retried": srv.retried,
+                "exact_over_estimate_max": round(max((r.bytes_exact / r.bytes_est for r in results
+                                                      if r.bytes_est and r.bytes_exact), default=0.0), 3),
                 "tuner_errors": {f"L{l} theta{t}": {p: float(f"{e:.3g}") for p, e in sorted(v.items())}
                                  for (l, t), v in sorted(tuner.errors.items())},
                 "choices": {f"n={n} tol={t:g}": list(tuner.choose(n, t)) for n in (1000, 20_000, 200_000)

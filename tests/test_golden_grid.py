@@ -26,3 +26,35 @@ def test_plummer16m_grid_golden():
         d1 = np.linalg.norm(v[12] - v[8]) / np.linalg.norm(v[16])
         d2 = np.linalg.norm(v[16] - v[12]) / np.linalg.norm(v[16])
         assert d2 < d1 / 10, (r["theta"], d1, d2)
+
+
+GOLDEN134 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer134m_leaves.json")
+
+
+def test_plummer134m_leaves_golden():
+    """The stored oracle values of the 2^27-point cloud (CPU): complete and
+    finite; every sampled leaf holds 64 points (2^27 over 8^7 leaves, the
+    closed form of the median splits) at consecutive tree positions 64 b;
+    and the settings, each within about 1e-6 of the true potential and
+    field, agree with each other to that order (theta 0.6 at p 12 and 13:
+    the change is below 1e-6 relative)."""
+    with open(GOLDEN134) as f:
+        doc = json.load(f)
+    leaves = doc["leaves"]
+    assert len(doc["points"]) == len(leaves) == len(doc["start"])
+    for b, s0, pts in zip(leaves, doc["start"], doc["points"]):
+        assert s0 == 64 * b and len(pts) == 64 and len(set(pts)) == 64
+        assert pts == sorted(pts) and all(0 <= i < 1 << 27 for i in pts)
+    npts = 64 * len(leaves)
+    vals = {}
+    for st in doc["settings"]:
+        v = np.array([st[k] for k in ("phi", "ex", "ey", "ez")])
+        assert v.shape == (4, npts) and np.all(np.isfinite(v))
+        assert all(c > 0 for c in st["chain_weak_pairs"][2:])  # levels 3..7 all contribute M2L
+        vals[(st["theta"], st["p"])] = v
+    a, b = vals[(0.6, 12)], vals[(0.6, 13)]
+    for k in range(4):
+        assert np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k]) < 2e-6
+    c = vals[(0.5, 12)]
+    for k in range(4):
+        assert np.linalg.norm(c[k] - b[k]) / np.linalg.norm(b[k]) < 2e-6

@@ -190,3 +190,49 @@ def test_plummer134m_full_size(torch, F):
         ephi, eE = rel(g, d)
         say(f"[large] plummer134m precision {prec}: phi {ephi:.2e} E {eE:.2e}")
         assert ephi <= 1e-6 and eE <= 1e-6
+
+
+GOLDEN134 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer134m_leaves.json")
+
+
+@pytest.fixture(scope="module")
+def plummer134m(torch, F):
+    """The 2^27-point workload on the device and the oracle's stored values
+    at every point of five sampled leaves (targeted-mode oracle)."""
+    x, y, z, q, w = W.workload("plummer134m")
+    X, Y, Z, Q = (dev(torch, a) for a in (x, y, z, q))
+    del x, y, z, q
+    with open(GOLDEN134) as f:
+        gold = json.load(f)
+    return X, Y, Z, Q, w["levels"], gold
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_plummer134m_sampled_leaves_match_the_oracle(torch, F, plummer134m, k):
+    """Oracle parity at the largest one-GPU size: the sampled leaves' point
+    ranges, point sets and cells bit for bit, and binary64 potential and field
+    at all their points within FP64_TOL of the oracle (which ran the whole
+    method along the chains of these leaves, tests/golden/make_plummer134m_leaves.py),
+    mixed precision within 1e-6."""
+    X, Y, Z, Q, L, gold = plummer134m
+    st = gold["settings"][k]
+    theta, p = st["theta"], st["p"]
+    say(f"[large] plummer134m vs oracle: theta {theta} p {p}")
+    gt = F.fmm_build(X, Y, Z, L, theta)
+    leaves = gold["leaves"]
+    geom, start = F.fmm_tree_boxes(gt, L)
+    perm = F.fmm_tree_perm(gt)
+    for b, s0, pts, cell in zip(leaves, gold["start"], gold["points"], gold["cell_hex"]):
+        assert start[b] == s0
+        assert np.array_equal(perm[start[b]:start[b + 1]], np.array(pts, dtype=np.int32))
+        assert [float(v).hex() for v in geom[b]] == cell
+    del perm
+    idx = torch.tensor(np.concatenate([np.array(a) for a in gold["points"]]), dtype=torch.int64, device="cuda")
+    ref = [np.array(st[c]) for c in ("phi", "ex", "ey", "ez")]
+    o = [torch.empty_like(X) for _ in range(4)]
+    for prec, tol in ((F.FMM_PREC_F64, FP64_TOL), (F.FMM_PREC_MIXED, 1e-6)):
+        F.fmm_evaluate_tree(gt, Q, p, *o, precision=prec)
+        torch.cuda.synchronize()
+        at = [a.index_select(0, idx).cpu().numpy() for a in o]
+        assert_close(at, ref, tol=tol, what=f"plummer134m theta {theta} p {p} precision {prec} vs oracle")
+    gt.free()

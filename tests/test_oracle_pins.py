@@ -541,3 +541,94 @@ def test_fmm_deep_tree_separate_targets_match_direct_sum(orc, levels, p):
     d = orc.direct(X, Y, Z, Q, targets=np.arange(x.size, x.size + tx.size))
     for u, v in zip(f, d):
         assert _relerr(u, v) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# The rotational M2L form (Section 2.1.3), threads and the targeted mode
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 7, 12, 15, 16, 20])
+def test_m2l_rotational_form_equals_basic_form(orc, p):
+    """Two independent derivations of the same operator: the translation
+    theorem in its basic O(p^4) form against rotation onto the z-axis,
+    z-translation and rotation back.  Directions include the poles (+z, -z),
+    the coordinate axes and general ones."""
+    rng = np.random.default_rng(100 + p)
+    x, y, z = rng.uniform(-0.3, 0.3, (3, 25))
+    q = rng.uniform(-1, 1, 25)
+    M = orc.p2m(p, (0.0, 0.0, 0.0), x, y, z, q)
+    dirs = [(0, 0, 2.5), (0, 0, -2.5), (2.2, 0, 0), (0, -2.2, 0), (1e-12, 0, 3.0), (-1.5, 1.5, 0.0)]
+    dirs += [tuple(2.5 * v / np.linalg.norm(v)) for v in rng.normal(size=(6, 3))]
+    for d in dirs:
+        a = orc.m2l(p, M, d)
+        b = orc.m2l_rot(p, M, d)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max(), d
+
+
+def test_fmm_rotational_form_same_result(orc):
+    x, y, z, q = W.gaussian_mixture(6000, seed=12)
+    t = orc.Tree(x, y, z, 3, 0.5)
+    leaves = np.arange(0, 512, 9)
+    a = t.evaluate(q, 9, leaves=leaves)
+    orc.set_m2l_form(True)
+    try:
+        b = t.evaluate(q, 9, leaves=leaves)
+    finally:
+        orc.set_m2l_form(False)
+    s, perm = t.start(3), t.perm()
+    pts = np.concatenate([perm[s[k]:s[k + 1]] for k in leaves])
+    for u, v in zip(a, b):
+        assert _relerr(v[pts], u[pts]) < 1e-13
+
+
+def test_oracle_threads_do_not_change_results(orc):
+    """Threads share out boxes, leaves and targets; each sum keeps its order,
+    so the results are bitwise those of one thread."""
+    x, y, z, q = W.plummer(9000, seed=4, charges="pm1")
+    tx, ty, tz, _ = W.uniform_cube(300, seed=5)
+    old = orc.set_threads(0)
+    try:
+        outs = []
+        for nt in (1, 4):
+            orc.set_threads(nt)
+            t = orc.Tree(x, y, z, 3, 0.5, targets=(tx, ty, tz))
+            outs.append((t.perm(), t.lists(3, 1), t.evaluate(q, 7), t.evaluate_targets(q, 7),
+                         orc.direct(x, y, z, q, targets=np.arange(0, 9000, 7))))
+        (pa, la, ea, ta, da), (pb, lb, eb, tb, db) = outs
+        assert np.array_equal(pa, pb)
+        assert np.array_equal(la[0], lb[0]) and np.array_equal(la[1], lb[1])
+        for u, v in zip(ea + ta + da, eb + tb + db):
+            assert np.array_equal(u, v)
+    finally:
+        orc.set_threads(old)
+
+
+def test_targeted_mode_equals_the_full_tree(orc):
+    """Targeted mode (lists only along the chains of chosen leaves): the rows
+    of the chain boxes equal the full tree's, every other row is empty, the
+    evaluation at the chosen leaves is bitwise the full one, and other leaves
+    are refused."""
+    x, y, z, q = W.plummer(30000, seed=8, charges="pm1")
+    leaves = np.array([0, 77, 300, 511])
+    full = orc.Tree(x, y, z, 3, 0.5)
+    tg = orc.Tree(x, y, z, 3, 0.5, leaves=leaves)
+    assert np.array_equal(full.perm(), tg.perm())
+    for l in range(1, 4):
+        anc = set((leaves // 8 ** (3 - l)).tolist())
+        for kind in (0, 1):
+            fo, fi = full.lists(l, kind)
+            to, ti = tg.lists(l, kind)
+            for b in range(8 ** l):
+                row_t = ti[to[b]:to[b + 1]]
+                if b in anc:
+                    assert np.array_equal(row_t, fi[fo[b]:fo[b + 1]])
+                else:
+                    assert row_t.size == 0
+    a = full.evaluate(q, 8, leaves=leaves)
+    b = tg.evaluate(q, 8, leaves=leaves)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v, equal_nan=True)
+    with pytest.raises(ValueError):
+        tg.evaluate(q, 8, leaves=np.array([1]))
+    with pytest.raises(ValueError):
+        tg.evaluate(q, 8)

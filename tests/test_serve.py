@@ -114,32 +114,101 @@ def test_tuner_model_is_monotone():
 
 
 class FakeServer(serve.Server):
-    """The admission logic with a solve that only sleeps (CPU)."""
+    """The admission logic with a solve that only sleeps (CPU).  Once its
+    'tree is built' a request reports exact bytes of `exact(rid)`; requests
+    listed in `fail_once` fail their first solve with FMM_ENOMEM."""
 
-    def solve(self, req, data, stream):
+    exact = None
+    fail_once = ()
+
+    def solve(self, req, data, stream, reserve=None):
+        if req.rid in self.fail_once and req.rid not in self._failed:
+            self._failed.add(req.rid)
+            raise serve.fmm.FMMError(serve.fmm.FMM_ENOMEM, "over budget")
+        if reserve is not None and self.exact is not None:
+            reserve(self.exact(req.rid))
+        with self._cv:
+            self.max_seen = max(getattr(self, "max_seen", 0), self._in_flight)
         time.sleep(0.001 * (1 + req.rid % 3))
         return serve.Result(req.rid, req.arrival)
+
+
+class _FakeEvent:
+    def __init__(self, **kw):
+        pass
+
+    def record(self, *a):
+        pass
+
+
+def _fake_torch(monkeypatch):
+    class FakeCuda:
+        Event = _FakeEvent
+
+        @staticmethod
+        def Stream():
+            return None
+
+        @staticmethod
+        def synchronize():
+            pass
+
+    import types
+    monkeypatch.setitem(__import__("sys").modules, "torch", types.SimpleNamespace(cuda=FakeCuda))
 
 
 def test_admission_respects_budget(monkeypatch):
     monkeypatch.setattr(serve.fmm, "fmm_bytes_estimate", lambda n, l, th, p: n)
     monkeypatch.setattr(serve, "request_points", lambda r: None)
-
-    class FakeCuda:
-        @staticmethod
-        def Stream():
-            return None
-
-    import types
-    fake_torch = types.SimpleNamespace(cuda=FakeCuda)
-    monkeypatch.setitem(__import__("sys").modules, "torch", fake_torch)
+    _fake_torch(monkeypatch)
     reqs = [serve.Request(i, 0.0, "uniform", 100 + 50 * (i % 5), 1e-4, i) for i in range(60)]
     srv = FakeServer(serve.Tuner(errors=SYNTH), workers=6, hbm_budget=500)
+    srv._failed = set()
     res = srv.run(reqs, realtime=False)
     assert sorted(r.rid for r in res) == list(range(60))
     assert all(not r.error for r in res)
     assert srv.peak_bytes <= 500
     assert srv.peak_concurrency >= 2  # requests overlap
+    assert srv.deferred > 0
+    assert srv._in_flight == 0 and srv._active == 0
+
+
+def test_admission_reaccounts_exact_bytes(monkeypatch):
+    """A request whose exact bytes (known after its build) exceed the
+    estimate raises the reservation: later admissions see the larger total,
+    and every byte is returned at the end."""
+    monkeypatch.setattr(serve.fmm, "fmm_bytes_estimate", lambda n, l, th, p: 100)
+    monkeypatch.setattr(serve, "request_points", lambda r: None)
+    _fake_torch(monkeypatch)
+    reqs = [serve.Request(i, 0.0, "uniform", 1000, 1e-4, i) for i in range(40)]
+    srv = FakeServer(serve.Tuner(errors=SYNTH), workers=6, hbm_budget=450)
+    srv._failed = set()
+    srv.exact = lambda rid: 300 if rid % 4 == 0 else 50
+    res = srv.run(reqs, realtime=False)
+    assert all(not r.error for r in res)
+    # the exact figures are what the server held: 300 + at most one estimate
+    # in flight before a 300-byte request's build reports
+    assert srv.peak_bytes >= 300
+    assert srv.max_seen <= 450 + 300
+    assert srv._in_flight == 0 and srv._active == 0
+
+
+def test_hard_budget_failure_runs_again(monkeypatch):
+    """With a hard budget a solve that fails with FMM_ENOMEM waits for the
+    running requests and runs again; it is reported once, without error."""
+    monkeypatch.setattr(serve.fmm, "fmm_bytes_estimate", lambda n, l, th, p: 10)
+    monkeypatch.setattr(serve, "request_points", lambda r: None)
+    monkeypatch.setattr(serve.fmm, "TorchAllocator", lambda budget: type("A", (), {"install": lambda self: self})())
+    monkeypatch.setattr(serve.fmm, "fmm_set_allocator", lambda *a: None)
+    _fake_torch(monkeypatch)
+    reqs = [serve.Request(i, 0.0, "uniform", 1000, 1e-4, i) for i in range(30)]
+    srv = FakeServer(serve.Tuner(errors=SYNTH), workers=4, hbm_budget=100, hard_budget=True)
+    srv._failed = set()
+    srv.fail_once = {3, 7, 11}
+    res = srv.run(reqs, realtime=False)
+    assert sorted(r.rid for r in res) == list(range(30))
+    assert all(not r.error for r in res)
+    assert srv.retried == 3 and sorted(r.rid for r in res if r.retries) == [3, 7, 11]
     assert srv._in_flight == 0 and srv._active == 0
 
 
@@ -161,3 +230,80 @@ def test_results_same_alone_and_in_the_mix():
         for u, v in zip(a.outputs, m.outputs):
             assert np.array_equal(u, v)
 
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.gpu
+def test_served_results_match_the_oracle(orc):
+    """Every served result against the CPU oracle at the parameters the tuner
+    chose for it (same tree, lists and order): binary64 requests within
+    1e-12, mixed-precision ones within 1e-6 (the binary32 M2L), normwise over
+    the points of sampled leaves.  Sizes lie on both sides of the chunked
+    bisection thresholds (8192, 16384); accuracies 1e-4 (mixed, p 5) and 1e-8
+    (binary64, p 18, the vector M2L) with the synthetic error table."""
+    torch = _gpu()
+    sizes = [3000, 8100, 8300, 12000, 16300, 17000, 21000]
+    reqs = [serve.Request(i, 0.0, serve.DISTRIBUTIONS[i % 3], n, tol, 7000 + i)
+            for i, (n, tol) in enumerate((n, tol) for n in sizes for tol in (1e-4, 1e-8))]
+    tuner = serve.Tuner(errors=SYNTH)
+    res = serve.Server(tuner, workers=4, keep_outputs=True).run(reqs, realtime=False)
+    for r, got in zip(reqs, res):
+        assert not got.error, got.error
+        L, theta, p, prec = got.params
+        x, y, z, q = serve.request_points(r)
+        t = orc.Tree(x, y, z, L, theta)
+        leaves = np.unique(np.linspace(0, 8 ** L - 1, 6).astype(np.int64))
+        ref = t.evaluate(q, p, leaves=leaves)
+        s, perm = t.start(L), t.perm()
+        pts = np.concatenate([perm[s[b]:s[b + 1]] for b in leaves])
+        tol = 1e-12 if prec == 0 else 1e-6
+        print(f"[serve-oracle] rid {r.rid} n {r.n} L {L} theta {theta} p {p} prec {prec}", flush=True)
+        for u, v in zip(got.outputs, ref):
+            err = np.linalg.norm(u[pts] - v[pts]) / np.linalg.norm(v[pts])
+            assert err <= tol, (r.rid, err)
+
+
+@pytest.mark.gpu
+def test_hard_budget_defers_and_results_unchanged():
+    """A device budget of about two requests: admission has to defer, the
+    library's allocations stay within the budget, and every result equals the
+    same request solved alone."""
+    torch = _gpu()
+    rng = np.random.default_rng(5)
+    reqs = [serve.Request(i, 0.0, serve.DISTRIBUTIONS[i % 3], int(rng.integers(20_000, 60_000)),
+                          1e-4, 8000 + i) for i in range(16)]
+    tuner = serve.Tuner(errors=SYNTH)
+    alone = serve.Server(tuner, workers=1, keep_outputs=True)
+    stream = torch.cuda.Stream()
+    ref = [alone.solve(r, serve.request_points(r), stream) for r in reqs]
+    budget = 2 * max(r.bytes_exact for r in ref)
+    srv = serve.Server(tuner, workers=6, keep_outputs=True, hbm_budget=budget, hard_budget=True)
+    res = srv.run(reqs, realtime=False)
+    print(f"[serve-budget] budget {budget} B, deferred {srv.deferred}, retried {srv.retried}, "
+          f"peak {srv.peak_bytes} B, library peak {srv._alloc.peak} B", flush=True)
+    assert srv.deferred > 0
+    assert srv._alloc.peak <= budget and srv._alloc.in_use == 0
+    for a, m in zip(ref, res):
+        assert not m.error, m.error
+        for u, v in zip(a.outputs, m.outputs):
+            assert np.array_equal(u, v)
+
+
+@pytest.mark.gpu
+def test_served_solves_overlap_on_the_device():
+    """With several workers the solves of different requests run on the
+    device at the same time (device timestamps of each solve)."""
+    _gpu()
+    rng = np.random.default_rng(9)
+    reqs = [serve.Request(i, 0.0, serve.DISTRIBUTIONS[i % 3], int(rng.integers(30_000, 100_000)),
+                          1e-4, 9000 + i) for i in range(24)]
+    res = serve.Server(serve.Tuner(errors=SYNTH), workers=6).run(reqs, realtime=False)
+    ov = serve.device_overlap(res)
+    print(f"[serve-overlap] {ov}", flush=True)
+    assert ov["max_concurrent"] >= 2 and ov["overlap_frac"] > 0.2
