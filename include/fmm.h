@@ -142,6 +142,32 @@ fmm_status fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int part
                          double* ey, double* ez, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation): as
+ * fmm_evaluate_tree_ex, but every scratch buffer of the evaluation is carved
+ * from one fixed device array of 64 MiB per GPU, held from the library's
+ * load until the process ends.  The call allocates nothing, records no event
+ * and never waits on the host, so it may be captured into a HIP graph.
+ *   - FMM_EINVAL when the evaluation needs more scratch than the array holds
+ *     (fmm_tree_bytes' eval_bytes plus alignment slack, checked before any
+ *     work is enqueued; about 2e5 points at 4 levels and p = 12 fit).
+ *   - FMM_EUNSUPPORTED when the operator tables of order p are not on the
+ *     device yet: one evaluation at order p through an allocating entry point
+ *     makes them.
+ *   - Every call on a GPU shares that GPU's array, and the array keeps the
+ *     last call's contents: calls that overlap on one GPU (other streams,
+ *     other threads, graph replays in flight) race and give wrong results.
+ *     Order them on one stream or wait in between.
+ *   - The tree's build must be complete on the device (or ordered before the
+ *     call on `stream`), and the tree must not be freed while work enqueued
+ *     by this call is pending: unlike the other entry points this one does
+ *     not track the streams that use the tree.
+ *   - Phase timing (fmm_set_profiling) does not cover this call.
+ */
+fmm_status fmm_evaluate_tree_noalloc(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot,
+                                     double* ex, double* ey, double* ez, void* stream);
+
+/*
  * fmm_build with the split parameter eta and separate evaluation targets
  * (Section 2.1.2; the convergence test of Section 3.1 evaluates at points
  * that are not sources).

@@ -17,6 +17,17 @@ struct fmm_tree {
 
 namespace fmm {
 
+// 1 if work enqueued on s is being captured into a graph
+bool capturing(hipStream_t s) {
+  if (!s) return false;  // the null stream is never captured
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
 namespace {
 thread_local std::string g_err;
 
@@ -170,10 +181,15 @@ void release(Tree& t) {
 
 // An evaluation on stream s: s first waits for the build when it is another
 // stream; afterwards the evaluation is recorded so that fmm_free can wait.
+// Under graph capture neither happens (no event may cross the capture): the
+// caller orders the build before the capture and keeps the tree alive while
+// the graph may run.
 void begin_use(Tree& t, hipStream_t s) {
+  if (capturing(s)) return;
   if (t.built && s != t.build_stream) HIPCHECK(hipStreamWaitEvent(s, t.built, 0));
 }
 void end_use(Tree& t, hipStream_t s) {
+  if (capturing(s)) return;
   hipEvent_t ev = nullptr;
   for (auto& u : t.uses)
     if (u.first == s) ev = u.second;
@@ -204,8 +220,18 @@ void check_hip(hipError_t e, const char* what) {
   fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+thread_local Arena* g_arena = nullptr;
+void set_arena(Arena* a) { g_arena = a; }
+
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 8;
+  if (g_arena) {
+    const size_t off = (g_arena->used + 255) & ~(size_t)255;
+    if (off > g_arena->size || bytes > g_arena->size - off)
+      fail(FMM_EINVAL, "evaluation scratch exceeds the fixed buffer of " + std::to_string(g_arena->size) + " bytes");
+    g_arena->used = off + bytes;
+    return g_arena->base + off;
+  }
   const Allocator a = g_ledger ? g_ledger->a : Allocator{};
   void* p = raw_alloc(a, bytes, s);
   if (!p) fail(FMM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
@@ -221,7 +247,7 @@ void* dalloc(size_t bytes, hipStream_t s) {
 }
 
 void dfree(void* p, hipStream_t s) {
-  if (!p) return;
+  if (!p || g_arena) return;
   const Allocator a = g_ledger ? g_ledger->a : Allocator{};
   if (g_ledger) {
     auto& v = g_ledger->live;
@@ -264,6 +290,12 @@ LevelView Tree::view() const {
 PhaseTimer& timer() {
   static thread_local PhaseTimer t;
   return t;
+}
+
+bool PhaseTimer::set_enabled(bool on) {
+  const bool was = g_tm.on;
+  g_tm.on = on;
+  return was;
 }
 
 void PhaseTimer::reset() {
@@ -374,6 +406,16 @@ void run_evaluation(fmm::Tree& t, hipStream_t s, F&& f) {
       }
     }
   } use{t, s};
+  struct Timer {
+    bool was;
+    bool cap;
+    explicit Timer(hipStream_t s) : was(false), cap(fmm::capturing(s)) {
+      if (cap) was = fmm::timer().set_enabled(false);  // no timing events inside a graph
+    }
+    ~Timer() {
+      if (cap) fmm::timer().set_enabled(was);
+    }
+  } tm{s};
   fmm::CallScope scope(fmm::current_allocator(), s);
   f();
 }
@@ -439,6 +481,17 @@ fmm_status fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int part
     if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
     hipStream_t s = (hipStream_t)stream;
     run_evaluation(t, s, [&] { fmm::evaluate(t, q, p, parts, precision, pot, ex, ey, ez, s); });
+  });
+}
+
+fmm_status fmm_evaluate_tree_noalloc(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot,
+                                     double* ex, double* ey, double* ez, void* stream) {
+  return fmm::guarded([&] {
+    fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
+    validate_eval_args(q, p, pot, ex, ey, ez);
+    if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
+    fmm::evaluate_noalloc(t, q, p, parts, precision, pot, ex, ey, ez, (hipStream_t)stream);
   });
 }
 

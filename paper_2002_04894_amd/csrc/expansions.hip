@@ -304,6 +304,13 @@ T* upload(const std::vector<T>& v, hipStream_t s) {
 
 }  // namespace
 
+bool tables_ready(int p) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  return g_tabs.count({dev, p}) != 0;
+}
+
 // The tables of order p on the current device, made on first use.  Later
 // calls use them from any stream, also non-blocking ones that do not order
 // after the null stream, and a synchronous copy from pageable memory may
@@ -315,6 +322,9 @@ const Tables& tables_for(int p, hipStream_t s) {
   std::lock_guard<std::mutex> g(g_tab_mu);
   auto it = g_tabs.find({dev, p});
   if (it != g_tabs.end()) return it->second;
+  if (capturing(s))
+    fail(FMM_EUNSUPPORTED, "the operator tables of order " + std::to_string(p) +
+                               " must be made (one evaluation at this order) before graph capture");
   HostTables h = make_host_tables(p);
   Tables t;
   t.p = p;

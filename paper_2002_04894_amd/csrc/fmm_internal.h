@@ -41,6 +41,20 @@ struct Allocator {
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 
+// Evaluation scratch carved from one fixed device buffer (the entry point
+// that allocates nothing): while an arena is set on this thread, dalloc hands
+// out 256-byte aligned slices of it (FMM_EINVAL when it runs out) and dfree
+// does nothing.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+};
+void set_arena(Arena* a);  // nullptr: back to the allocator
+
+// 1 if work enqueued on s is being captured into a graph
+bool capturing(hipStream_t s);
+
 // Per-thread pinned host words for small device-to-host read-backs (made
 // once per thread; kStageWords int64 values).
 constexpr int kStageWords = 64;
@@ -139,12 +153,15 @@ struct Tables {
   bool tiled = false;
 };
 const Tables& tables_for(int p, hipStream_t s);
+// the tables of order p exist on the current device (no allocation, no wait)
+bool tables_ready(int p);
 
 // Phase timer (HIP events), per thread.
 struct PhaseTimer {
   void begin(int phase, hipStream_t s);
   void end(int phase, hipStream_t s);
   void reset();
+  bool set_enabled(bool on);  // returns the previous setting
 };
 PhaseTimer& timer();
 
@@ -163,6 +180,13 @@ void evaluate_targets(const Tree& t, const double* q, int p, int parts, int prec
                       double* ez, hipStream_t s);
 void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex, double* ey, double* ez,
               hipStream_t s);
+
+// evaluate() with its scratch in the device's fixed scratch array (no
+// allocation, no event, no host wait); FMM_EINVAL beyond the array's size,
+// FMM_EUNSUPPORTED when the order's tables are not made yet
+void evaluate_noalloc(const Tree& t, const double* q, int p, int parts, int prec, double* pot, double* ex,
+                      double* ey, double* ez, hipStream_t s);
+size_t noalloc_scratch_bytes();
 
 // peak scratch bytes of one evaluation (evaluate, plus evaluate_targets when
 // the tree has targets) at order p and precision prec

@@ -45,29 +45,17 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 // radius-scaled expansions: R is the arithmetic type of the translations.
 template <class R>
 struct Ar;
-// kWaves: waves per block sharing one target's batches (their operand
-// fragments split between them); kWavesPerEu: the occupancy asked for.
 template <>
 struct Ar<double> {
   typedef d4 v4;
   typedef d2 v2;
   static constexpr int kRowStride = 18;  // pair-sum rows: 144 B, no bank conflicts
-  static constexpr int kWaves = 2;
-  static constexpr int kWavesPerEu = 2;
 };
-#ifndef FMM_M2L_F32_WAVES
-#define FMM_M2L_F32_WAVES 2
-#endif
-#ifndef FMM_M2L_F32_WAVES_PER_EU
-#define FMM_M2L_F32_WAVES_PER_EU 2
-#endif
 template <>
 struct Ar<float> {
   typedef f4 v4;
   typedef f2 v2;
   static constexpr int kRowStride = 20;
-  static constexpr int kWaves = FMM_M2L_F32_WAVES;
-  static constexpr int kWavesPerEu = FMM_M2L_F32_WAVES_PER_EU;
 };
 
 // Orders this wave's LDS accesses around a point (other lanes of the wave
@@ -98,8 +86,7 @@ struct Cfg {
   // the two waves' pair-sum rounds reuse it
   static constexpr int ZDUMMY = ZR;
   static constexpr int RSTRIDE = Ar<R>::kRowStride;
-  static constexpr int NWV = Ar<R>::kWaves;
-  static constexpr int ZBUF = 16 * (ZR + 3) > NWV * 64 * RSTRIDE ? 16 * (ZR + 3) : NWV * 64 * RSTRIDE;
+  static constexpr int ZBUF = 16 * (ZR + 3) > 2 * 64 * RSTRIDE ? 16 * (ZR + 3) : 2 * 64 * RSTRIDE;
   // per pair: (cos, sin)(m (theta + pi)), (cos, sin)(m (alpha + pi)), m = 0..P;
   // 16 more bytes per pair so that the 16 pair columns hit different banks
   static constexpr int TRIG = 4 * (P + 1) + 2;
@@ -118,37 +105,36 @@ __host__ __device__ constexpr int split_na() {
   const int na = (2 * NP + 2 - MX + 2) / 4;
   return na < NP ? na : NP;
 }
-template <int P, int NW>
+template <int P>
 __host__ __device__ constexpr int tile_owner(int t) {
   constexpr int NP = tl::npairs(P);
-  if (NW == 1) return 0;  // one wave per block owns every tile
   if (t < 2 * NP) return (t < NP ? t : t - NP) < split_na<P>() ? 0 : 1;
   if (tl::has_mixed(P) && t == tl::mixed_tile(P)) return 0;
   return 1;
 }
-template <int P, int NW>
+template <int P>
 __host__ __device__ constexpr int tiles_of(int w) {
   int c = 0;
-  for (int t = 0; t < tl::ntiles(P); ++t) c += tile_owner<P, NW>(t) == w ? 1 : 0;
+  for (int t = 0; t < tl::ntiles(P); ++t) c += tile_owner<P>(t) == w ? 1 : 0;
   return c;
 }
 // k-th tile (in tile order) owned by wave w
-template <int P, int NW>
+template <int P>
 __host__ __device__ constexpr int owned_tile(int w, int k) {
   for (int t = 0; t < tl::ntiles(P); ++t)
-    if (tile_owner<P, NW>(t) == w && k-- == 0) return t;
+    if (tile_owner<P>(t) == w && k-- == 0) return t;
   return 0;
 }
 struct MSplit {
   int owner[tl::kMaxP + 1];
 };
-template <int P, int NW>
+template <int P>
 __host__ __device__ constexpr MSplit m_split() {
   MSplit r{};
-  int load[2] = {16 * tiles_of<P, NW>(0), 16 * tiles_of<P, NW>(1)};  // four J products of four steps per tile
+  int load[2] = {16 * tiles_of<P>(0), 16 * tiles_of<P>(1)};  // four J products of four steps per tile
   // orders by decreasing work: low m first (more rows)
   for (int m = 0; m <= P; ++m) {
-    const int w = (NW == 1 || load[0] <= load[1]) ? 0 : 1;
+    const int w = load[0] <= load[1] ? 0 : 1;
     r.owner[m] = w;
     load[w] += tl::hsteps(P, m) * (m == 0 ? 1 : 2);
   }
@@ -281,7 +267,7 @@ __device__ __forceinline__ void rotz(typename Ar<R>::v4* st, const R* cs, R sgn,
   };
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
-    if (tile_owner<P, Ar<R>::kWaves>(a) != W) continue;
+    if (tile_owner<P>(a) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       R c = st[a][i], s = st[NP + a][i];
@@ -290,7 +276,7 @@ __device__ __forceinline__ void rotz(typename Ar<R>::v4* st, const R* cs, R sgn,
       st[NP + a][i] = s;
     }
   }
-  if constexpr (tl::has_mixed(P) && tile_owner<P, Ar<R>::kWaves>(tl::mixed_tile(P)) == W) {
+  if constexpr (tl::has_mixed(P) && tile_owner<P>(tl::mixed_tile(P)) == W) {
     constexpr int t = tl::mixed_tile(P);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -300,7 +286,7 @@ __device__ __forceinline__ void rotz(typename Ar<R>::v4* st, const R* cs, R sgn,
       st[t][i + 2] = s;
     }
   }
-  if constexpr (tile_owner<P, Ar<R>::kWaves>(tl::top_c(P)) == W) {
+  if constexpr (tile_owner<P>(tl::top_c(P)) == W) {
     constexpr int tc = tl::top_c(P), ts = tl::top_s(P);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -319,7 +305,7 @@ __device__ __forceinline__ void japply(typename Ar<R>::v4* st, const R* jr) {
   constexpr int T = tl::ntiles(P);
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    if (tile_owner<P, Ar<R>::kWaves>(t) != W) continue;
+    if (tile_owner<P>(t) != W) continue;
     typename Ar<R>::v4 d = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -360,11 +346,11 @@ template <int P, int W, int SINE, class R>
 __device__ __forceinline__ void ztrans_part(typename Ar<R>::v4* st, const ZView<R>& z, R* zcol, const R* hr,
                                             int lane) {
   constexpr int T = tl::ntiles(P);
-  constexpr MSplit ms = m_split<P, Ar<R>::kWaves>();
+  constexpr MSplit ms = m_split<P>();
   const int g = lane >> 4;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    if (tile_owner<P, Ar<R>::kWaves>(t) != W) continue;
+    if (tile_owner<P>(t) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE || all_pad<P>(t, i)) continue;
@@ -391,7 +377,7 @@ __device__ __forceinline__ void ztrans_part(typename Ar<R>::v4* st, const ZView<
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    if (tile_owner<P, Ar<R>::kWaves>(t) != W) continue;
+    if (tile_owner<P>(t) != W) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (reg_sine<P>(t, i) != SINE || all_pad<P>(t, i)) continue;
@@ -416,9 +402,9 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
   constexpr bool MIXED = sizeof(R) == 4;
   constexpr int T = C::T;
   constexpr int S = C::S;
-  constexpr int NTW = tiles_of<P, Ar<R>::kWaves>(W);
+  constexpr int NTW = tiles_of<P>(W);
   constexpr int NRW = (NTW + 3) / 4;  // pair-sum rounds of four tiles
-  constexpr MSplit ms = m_split<P, Ar<R>::kWaves>();
+  constexpr MSplit ms = m_split<P>();
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, g = lane >> 4;
   R* trig = smem;                       // two tables, alternate batches
@@ -430,7 +416,7 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
   R jr[T * 4];
 #pragma unroll
   for (int t = 0; t < T; ++t)
-    if (tile_owner<P, Ar<R>::kWaves>(t) == W)
+    if (tile_owner<P>(t) == W)
 #pragma unroll
       for (int k = 0; k < 4; ++k) jr[t * 4 + k] = kstep_used<P>(t, k) ? mtab[(t * 4 + k) * 64 + lane] : (R)0;
   R hr[C::H];
@@ -507,13 +493,11 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
       }
       R* tp = trig + buf * 16 * C::TRIG + r16 * C::TRIG;  // this lane's pair
       // (cos, sin)(m (angle + pi)) by the angle-addition recurrence (binary64):
-      // with two waves wave 0 builds the theta table and wave 1 the alpha
-      // table (the four lane groups write the same values to the same words);
-      // with one wave lane groups 0, 1 build the theta table and 2, 3 the alpha one
+      // wave 0 builds the theta table, wave 1 the alpha table (the four lane
+      // groups write the same values to the same words)
       {
-        const bool alpha_tab = Ar<R>::kWaves == 1 ? g >= 2 : W == 1;
         double c1, s1;
-        if (!alpha_tab) {
+        if (W == 0) {
           const double irxy = rxy > 0.0 ? 1.0 / rxy : 0.0;
           c1 = -dy * irxy;
           s1 = rxy > 0.0 ? -dx * irxy : -1.0;
@@ -521,7 +505,7 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
           c1 = -dz * irho;
           s1 = -rxy * irho;
         }
-        R* dst = tp + (alpha_tab ? 2 * (P + 1) : 0);
+        R* dst = tp + (W == 0 ? 0 : 2 * (P + 1));
         double c = 1.0, s = 0.0;
 #pragma unroll
         for (int m = 0; m <= P; ++m) {
@@ -535,7 +519,7 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
       const R* src = Mlev + (size_t)j * S + 4 * g;
 #pragma unroll
       for (int t = 0; t < T; ++t)
-        if (tile_owner<P, Ar<R>::kWaves>(t) == W) st[t] = *(const v4*)(src + 16 * t);
+        if (tile_owner<P>(t) == W) st[t] = *(const v4*)(src + 16 * t);
       __syncthreads();  // both tables written
 
       // (cos, sin) tables shifted so that entry 2 (m0 + 4) is order m0 + g
@@ -563,7 +547,7 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (4 * r + q >= NTW) continue;
-          const int t = owned_tile<P, Ar<R>::kWaves>(W, 4 * r + q);
+          const int t = owned_tile<P>(W, 4 * r + q);
 #pragma unroll
           for (int i = 0; i < 4; ++i) red[(q * 16 + 4 * i + g) * C::RSTRIDE + r16] = st[t][i];
         }
@@ -585,7 +569,7 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
     for (int r = 0; r < NRW; ++r) {
       const int k = 4 * r + (lane >> 4);
       if (k < NTW) {
-        const int t = owned_tile<P, Ar<R>::kWaves>(W, k);
+        const int t = owned_tile<P>(W, k);
         const Pos d = slot_pos<P>(t, lane & 15);
         double v = (d.m & 1) ? -acc[r] : acc[r];
         if (MIXED) {
@@ -599,15 +583,14 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
 }
 
 template <int P, class R>
-__global__ __launch_bounds__(64 * Ar<R>::kWaves) __attribute__((amdgpu_waves_per_eu(Ar<R>::kWavesPerEu,
-                                                                                    Ar<R>::kWavesPerEu))) void
-k_m2l_mfma(LevelView lv, const R* __restrict__ mtab, const R* __restrict__ Mx, double* __restrict__ Lx,
-           int64_t ntarget, const int32_t* __restrict__ order, int* __restrict__ queue) {
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_m2l_mfma(
+    LevelView lv, const R* __restrict__ mtab, const R* __restrict__ Mx, double* __restrict__ Lx,
+    int64_t ntarget, const int32_t* __restrict__ order, int* __restrict__ queue) {
   __shared__ R smem[Cfg<P, R>::LDS];
   // every LDS word starts finite: buffer tails are read (and multiplied by 0)
-  for (int k = threadIdx.x; k < Cfg<P, R>::LDS; k += 64 * Ar<R>::kWaves) smem[k] = (R)0;
+  for (int k = threadIdx.x; k < Cfg<P, R>::LDS; k += 128) smem[k] = (R)0;
   __syncthreads();
-  if (Ar<R>::kWaves == 1 || threadIdx.x < 64)
+  if (threadIdx.x < 64)
     m2l_wave<P, 0, R>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
   else
     m2l_wave<P, 1, R>(smem, lv, mtab, Mx, Lx, ntarget, order, queue);
@@ -631,6 +614,10 @@ __global__ void k_scale_m32(LevelView lv, int S, const int8_t* __restrict__ sdeg
   }
 }
 
+__global__ void k_zero_queue(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
+}
+
 template <int P, class R>
 void launch_one(const Tree& t, const Tables& tb, const R* Mx, double* Lx, hipStream_t s) {
   const int64_t ntarget = t.nbox_total - 1;
@@ -640,19 +627,21 @@ void launch_one(const Tree& t, const Tables& tb, const R* Mx, double* Lx, hipStr
     int dev = 0, ncu = 0, per = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P, R>, 64 * Ar<R>::kWaves, 0));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_mfma<P, R>, 128, 0));
     return ncu * (per > 0 ? per : 1);
   }();
   const int64_t need = ntarget;
   const unsigned grid = (unsigned)(need < grid_max ? need : grid_max);
   int* queue = (int*)dalloc(sizeof(int), s);
-  HIPCHECK(hipMemsetAsync(queue, 0, sizeof(int), s));
+  // cleared by a kernel, not a memset node, so that the launch may be captured in a graph
+  k_zero_queue<<<1, 64, 0, s>>>(queue);
+  HIPCHECK(hipGetLastError());
   const R* mt;
   if constexpr (sizeof(R) == 4)
     mt = tb.mtab32;
   else
     mt = tb.mtab;
-  k_m2l_mfma<P, R><<<grid, 64 * Ar<R>::kWaves, 0, s>>>(t.view(), mt, Mx, Lx, ntarget, t.m2l_order, queue);
+  k_m2l_mfma<P, R><<<grid, 128, 0, s>>>(t.view(), mt, Mx, Lx, ntarget, t.m2l_order, queue);
   HIPCHECK(hipGetLastError());
   dfree(queue, s);
 }

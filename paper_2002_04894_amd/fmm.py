@@ -67,10 +67,12 @@ def lib():
     L.fmm_bytes_estimate.restype = C.c_size_t
     L.fmm_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
     L.fmm_tree_bytes.argtypes = [vp, i32, i32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    L.fmm_evaluate_tree_noalloc.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp]
     for f in ("fmm_build", "fmm_build_ex", "fmm_evaluate_targets", "fmm_tree_targets", "fmm_evaluate_tree_ex",
               "fmm_evaluate_tree", "fmm_evaluate_tree_parts", "fmm_evaluate", "fmm_free",
               "fmm_tree_info", "fmm_tree_perm", "fmm_tree_boxes", "fmm_tree_lists", "fmm_tree_stats",
-              "fmm_set_profiling", "fmm_last_timings", "fmm_set_allocator", "fmm_tree_bytes"):
+              "fmm_set_profiling", "fmm_last_timings", "fmm_set_allocator", "fmm_tree_bytes",
+              "fmm_evaluate_tree_noalloc"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -195,6 +197,18 @@ def fmm_evaluate_tree(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts
     else:
         _check(lib().fmm_evaluate_tree_parts(tree.handle, _ptr(q), int(p), int(parts), _ptr(pot), _ptr(ex),
                                              _ptr(ey), _ptr(ez), _stream(stream)))
+
+
+def fmm_evaluate_tree_noalloc(tree: Tree, q, p: int, pot, ex, ey, ez, stream=None, parts: int = FMM_PART_ALL,
+                              precision: int = FMM_PREC_F64):
+    """fmm_evaluate_tree with all scratch in the library's fixed device array
+    (no allocation; capturable in a graph; calls on one GPU must not overlap)."""
+    for t, nm in ((q, "q"), (pot, "pot"), (ex, "ex"), (ey, "ey"), (ez, "ez")):
+        _dev(t, nm)
+        if t.numel() != tree.n:
+            raise ValueError(f"{nm} must have {tree.n} elements")
+    _check(lib().fmm_evaluate_tree_noalloc(tree.handle, _ptr(q), int(p), int(parts), int(precision), _ptr(pot),
+                                           _ptr(ex), _ptr(ey), _ptr(ez), _stream(stream)))
 
 
 def fmm_evaluate(x, y, z, q, theta: float, p: int, levels: int, pot, ex, ey, ez, stream=None):
