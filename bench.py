@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--fixed", action="store_true",
                     help="time the workload's fixed theta and p in binary64 instead of the autotuned setting")
     ap.add_argument("--tol", type=float, default=1e-6, help="accuracy the autotuner must reach")
+    ap.add_argument("--setting", default="",
+                    help="THETA,P,PRECISION (f64 or mixed): time this setting, skipping the autotuner "
+                         "(for profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--f64-steps", type=int, default=3,
                     help="steps of the binary64 leg beside the autotuned (mixed) one (0: skip)")
@@ -118,6 +121,11 @@ def main():
     if args.fixed:
         tune = {"theta": w["theta"], "p": w["p"], "precision": fmm.FMM_PREC_F64}
         tuned_info = None
+    elif args.setting:
+        th_s, p_s, pr_s = args.setting.split(",")
+        tune = {"theta": float(th_s), "p": int(p_s),
+                "precision": fmm.FMM_PREC_MIXED if pr_s == "mixed" else fmm.FMM_PREC_F64}
+        tuned_info = None
     else:
         tune, tuned_info = autotune(X, Y, Z, Q, L, args.tol, stream, torch)
     theta, p, prec = tune["theta"], tune["p"], tune["precision"]
@@ -141,7 +149,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "levels": L, "theta": theta, "p": p,
                    "precision": "mixed" if mixed_path else "f64", "generator": w["gen"], "seed": w["seed"],
-                   "tuned": not args.fixed},
+                   "tuned": tuned_info is not None},
         "phase_ms": leg["phase_ms"],
         "p2p": leg["p2p"],
         "roofline": leg["roofline"],
@@ -151,7 +159,7 @@ def main():
     line["accuracy"] = gpu_direct_gate(X, Y, Z, Q, outs, torch)
     if tuned_info is not None:
         line["autotune"] = tuned_info
-    if args.f64_steps > 0 and prec != fmm.FMM_PREC_F64:
+    if args.f64_steps > 0 and prec != fmm.FMM_PREC_F64 and tuned_info is not None:
         f = tuned_info["f64_choice"]
         fouts = [torch.empty_like(X) for _ in range(4)]
         fl = timed_leg(X, Y, Z, Q, L, f["theta"], f["p"], fmm.FMM_PREC_F64, fouts, args.f64_steps, 1, stream,

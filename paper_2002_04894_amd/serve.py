@@ -432,6 +432,91 @@ class Server:
         return sorted(results, key=lambda r: r.rid)
 
 
+class GraphBatch:
+    """Many built trees evaluated by one launch of a captured HIP graph
+    (small instances fused; the paper reuses a tree for new charges, Section 4).
+
+    items: (tree, q, p, precision, outs) per instance, with q and the four
+    outputs device tensors that stay alive as long as the batch.  The
+    evaluations are captured once; every replay re-runs all of them with the
+    current contents of the q tensors and writes the outputs.  The kernels are
+    those of a solo evaluation, so the results are bitwise the same.
+
+    branches = 1: one chain through the entry point that allocates nothing
+    (fmm_evaluate_tree_noalloc; its fixed scratch array is shared, so no other
+    no-allocation call may run while a replay is in flight).
+    branches > 1: instance k runs on branch k % branches, the branches
+    concurrently (streams forked from the capture stream and joined again);
+    each branch has its own workspace, handed out during capture by an
+    allocator hook (fmm_set_allocator) that the batch installs and removes
+    again (the default pool is restored afterwards).
+
+    Every order and precision must have been evaluated once through an
+    allocating entry point before capture (its operator tables), and the
+    trees' builds must be complete."""
+
+    def __init__(self, items, branches: int = 1):
+        import torch
+        self._torch = torch
+        self.items = list(items)
+        self.branches = nb = max(1, min(int(branches), len(self.items)))
+        self.graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        cap = torch.cuda.Stream()
+        if nb == 1:
+            with torch.cuda.graph(self.graph, stream=cap):
+                self._enqueue()
+            torch.cuda.synchronize()
+            return
+        # per branch: its instances' scratch, summed over one evaluation's
+        # requests (at most twice the peak), plus alignment slack
+        need = [0] * nb
+        for k, (tree, q, p, prec, outs) in enumerate(self.items):
+            need[k % nb] = max(need[k % nb], 2 * fmm.fmm_tree_bytes(tree, p, prec)[1] + (64 << 10))
+        self._ws = [torch.empty(n, dtype=torch.uint8, device="cuda") for n in need]
+        self._streams = [torch.cuda.Stream() for _ in range(nb)]
+        base = {int(s.cuda_stream): (int(w.data_ptr()), w.numel()) for s, w in zip(self._streams, self._ws)}
+        used = {h: 0 for h in base}
+
+        def alloc(nbytes, stream):
+            b0, size = base[stream]
+            off = (used[stream] + 255) & ~255
+            if off + nbytes > size:
+                return 0
+            used[stream] = off + nbytes
+            return b0 + off
+
+        fmm.fmm_set_allocator(alloc, lambda ptr, stream: None)
+        try:
+            with torch.cuda.graph(self.graph, stream=cap):
+                for s in self._streams:
+                    s.wait_stream(cap)
+                for k, (tree, q, p, prec, outs) in enumerate(self.items):
+                    s = self._streams[k % nb]
+                    used[int(s.cuda_stream)] = 0  # the branch's previous instance is ordered before
+                    fmm.fmm_evaluate_tree(tree, q, p, *outs, stream=s, precision=prec)
+                for s in self._streams:
+                    cap.wait_stream(s)
+        finally:
+            fmm.fmm_set_allocator()
+        torch.cuda.synchronize()
+
+    def _enqueue(self):
+        for tree, q, p, prec, outs in self.items:
+            fmm.fmm_evaluate_tree_noalloc(tree, q, p, *outs, precision=prec)
+
+    def replay(self):
+        """Enqueue every evaluation of the batch (one graph launch) on the
+        current stream."""
+        self.graph.replay()
+
+    def eager(self):
+        """The same evaluations launched one call at a time on the current
+        stream (for comparison)."""
+        for tree, q, p, prec, outs in self.items:
+            fmm.fmm_evaluate_tree(tree, q, p, *outs, precision=prec)
+
+
 def device_overlap(results: list[Result]) -> dict:
     """From the device start/end of every solve: the time with at least one
     solve on the device, and the share of it with two or more at once."""
