@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -256,16 +257,15 @@ def rel_diff(a, b, torch):
     return dphi, dE
 
 
-def autotune(X, Y, Z, Q, L, tol, stream, torch, thetas=(0.5, 0.6, 0.7)) -> tuple[dict, dict]:
+def autotune(X, Y, Z, Q, L, tol, stream, torch, thetas=(0.5, 0.55, 0.6, 0.65, 0.7)) -> tuple[dict, dict]:
     """theta and p (and the precision) for accuracy `tol` on this workload,
     chosen by measurement (Section 3.2: the response to the parameters is
     convex, so a small search finds the optimum):
       1. a proxy of the workload -- every 64th point, 2 levels fewer (the
          same points per leaf) -- gives the error of every (theta, p) against
-         its direct sum at 10,000 points, in binary64 and mixed precision;
+         its direct sum at 10,000 points, in mixed precision;
       2. per theta the smallest order whose proxy error is within tol / 2,
-         timed for one step on the workload itself, mixed precision allowed
-         where the proxy shows it within tol / 2 too;
+         timed for one step on the workload itself;
       3. the fastest of these whose error on the workload, against the direct
          sum at 10,000 sampled points, is within tol wins; a candidate that
          misses tol is retried one order higher.
@@ -284,15 +284,18 @@ def autotune(X, Y, Z, Q, L, tol, stream, torch, thetas=(0.5, 0.6, 0.7)) -> tuple
     orders = range(4, 16)
     proxy = {}
     o = [torch.empty_like(Xs) for _ in range(4)]
-    for th in thetas:
+
+    def probe(th, precs):
         tr = fmm.fmm_build(Xs, Ys, Zs, Lp, th, stream)
         for p in orders:
-            for prec in (fmm.FMM_PREC_F64, fmm.FMM_PREC_MIXED):
+            for prec in precs:
                 fmm.fmm_evaluate_tree(tr, Qs, p, *o, stream, precision=prec)
                 g = [a.index_select(0, tgi).cpu().numpy() for a in o]
                 proxy[(th, p, prec)] = max(rel_err(g, ref))
         tr.free()
-    del o
+
+    for th in thetas:
+        probe(th, (fmm.FMM_PREC_MIXED,))
     cal_proxy_s = time.perf_counter() - t0
     log(f"autotune: proxy of {ns} points at {Lp} levels, {len(proxy)} settings in {cal_proxy_s:.1f} s")
 
@@ -301,7 +304,7 @@ def autotune(X, Y, Z, Q, L, tol, stream, torch, thetas=(0.5, 0.6, 0.7)) -> tuple
 
     def first_order(th, prec):
         for p in orders:
-            if proxy[(th, p, prec)] <= tol / 2:
+            if proxy.get((th, p, prec), math.inf) <= tol / 2:
                 return p
         return None
 
@@ -322,16 +325,15 @@ def autotune(X, Y, Z, Q, L, tol, stream, torch, thetas=(0.5, 0.6, 0.7)) -> tuple
         log(f"autotune: theta={th} p={p} {rec['precision']}: {rec['ms']:.0f} ms, error {err:.2e}")
         return rec
 
-    # mixed precision allowed: per theta the smallest order whose proxy error
-    # is within tol / 2 in mixed precision (else binary64), one timed step
-    # each on the workload; the fastest that meets tol on it wins
+    # mixed precision: per theta the smallest order whose proxy error is
+    # within tol / 2, one timed step each on the workload; the fastest that
+    # meets tol on it wins
     best = None
     for th in thetas:
-        cands = [(first_order(th, pr), pr) for pr in (fmm.FMM_PREC_MIXED, fmm.FMM_PREC_F64)]
-        cands = [(p, pr) for p, pr in cands if p is not None]
-        if not cands:
+        p = first_order(th, fmm.FMM_PREC_MIXED)
+        if p is None:
             continue
-        p, pr = cands[0]
+        pr = fmm.FMM_PREC_MIXED
         for _ in range(2):
             rec = run(th, p, pr)
             if rec["err"] <= tol:
@@ -345,6 +347,7 @@ def autotune(X, Y, Z, Q, L, tol, stream, torch, thetas=(0.5, 0.6, 0.7)) -> tuple
         raise RuntimeError(f"no setting reached {tol} on this workload")
     # binary64 only: the winner's theta at the smallest binary64 order whose
     # proxy error is within tol / 2 (its own accuracy is reported by its leg)
+    probe(best["theta"], (fmm.FMM_PREC_F64,))
     p64 = first_order(best["theta"], fmm.FMM_PREC_F64) or 15
     report = {"tol": tol, "proxy": {"points": ns, "levels": Lp, "settings": len(proxy), "seconds": round(cal_proxy_s, 2)},
               "tried": tried, "seconds": round(time.perf_counter() - t0, 2),

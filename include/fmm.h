@@ -124,6 +124,7 @@ fmm_status fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int p
 /* Arithmetic of the evaluation (fmm_evaluate_tree_ex). */
 #define FMM_PREC_F64 0   /* every step in IEEE binary64 */
 #define FMM_PREC_MIXED 1 /* M2L in binary32 (see below); the rest in binary64 */
+#define FMM_PREC_F32 2   /* M2L and the near field (P2P) in binary32 (see below) */
 
 /*
  * As fmm_evaluate_tree_parts, with a choice of arithmetic.  FMM_PREC_MIXED
@@ -131,12 +132,20 @@ fmm_status fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int p
  * p <= 15: the multipoles are scaled by powers of their box radius, so that
  * every translation factor (r_source/rho)^n, (r_target/rho)^j is below one;
  * the rotations and the z-axis translation run on the binary32 matrix cores;
- * the 16 pairs of a batch are summed in binary32 and the batches in binary64;
+ * the 16 pair results of a batch and the batches are summed in binary64;
  * the local expansions are unscaled into binary64.  The tree, P2M, M2M, L2L,
  * L2P and the near field (P2P) stay in binary64, as do all final sums.  The
  * far field then differs from the binary64 one by about 1e-7 relative
  * (normwise) on the workloads tested.  Higher orders run in binary64.
- * Returns FMM_EINVAL for an unknown precision.
+ * FMM_PREC_F32 also evaluates the near field (P2P, Algorithm 4) in binary32:
+ * coordinates relative to the target leaf's cell centre (formed in binary64,
+ * then rounded), the binary32 reciprocal square root, binary32 sums over each
+ * staged chunk of sources added into Kahan-compensated binary32 totals, which
+ * are widened to binary64 before the far field is added.  Its field differs
+ * from the binary64 one by up to a few 1e-5 relative on clustered clouds
+ * (cancellation among near contributions): it is meant for loose tolerances.
+ * Two distinct points whose relative binary32 coordinates coincide count as
+ * coincident.  Returns FMM_EINVAL for an unknown precision.
  */
 fmm_status fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int parts, int precision, double* pot, double* ex,
                          double* ey, double* ez, void* stream);

@@ -455,7 +455,8 @@ fmm_status fmm_evaluate_targets(fmm_tree* tree, const double* q, int p, int part
     if (p < 0 || p > FMM_MAX_ORDER) fail(FMM_EINVAL, "p must be in [0, 20]");
     if (t.m > 0 && (!pot || !ex || !ey || !ez)) fail(FMM_EINVAL, "output pointer is NULL");
     if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
-    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED && precision != FMM_PREC_F32)
+      fail(FMM_EINVAL, "unknown precision");
     hipStream_t s = (hipStream_t)stream;
     run_evaluation(t, s, [&] { fmm::evaluate_targets(t, q, p, parts, precision, pot, ex, ey, ez, s); });
   });
@@ -478,7 +479,8 @@ fmm_status fmm_evaluate_tree_ex(fmm_tree* tree, const double* q, int p, int part
     fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
     validate_eval_args(q, p, pot, ex, ey, ez);
     if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
-    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED && precision != FMM_PREC_F32)
+      fail(FMM_EINVAL, "unknown precision");
     hipStream_t s = (hipStream_t)stream;
     run_evaluation(t, s, [&] { fmm::evaluate(t, q, p, parts, precision, pot, ex, ey, ez, s); });
   });
@@ -490,7 +492,8 @@ fmm_status fmm_evaluate_tree_noalloc(fmm_tree* tree, const double* q, int p, int
     fmm::Tree& t = const_cast<fmm::Tree&>(get(tree));
     validate_eval_args(q, p, pot, ex, ey, ez);
     if (parts < 1 || parts > 3) fail(FMM_EINVAL, "parts must be 1, 2 or 3");
-    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED && precision != FMM_PREC_F32)
+      fail(FMM_EINVAL, "unknown precision");
     fmm::evaluate_noalloc(t, q, p, parts, precision, pot, ex, ey, ez, (hipStream_t)stream);
   });
 }
@@ -601,7 +604,8 @@ fmm_status fmm_tree_bytes(const fmm_tree* tree, int p, int precision, size_t* tr
   return fmm::guarded([&] {
     const fmm::Tree& t = get(tree);
     if (p < 0 || p > FMM_MAX_ORDER) fail(FMM_EINVAL, "p must be in [0, 20]");
-    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED) fail(FMM_EINVAL, "unknown precision");
+    if (precision != FMM_PREC_F64 && precision != FMM_PREC_MIXED && precision != FMM_PREC_F32)
+      fail(FMM_EINVAL, "unknown precision");
     if (tree_bytes) *tree_bytes = t.bytes;
     if (eval_bytes) *eval_bytes = fmm::eval_scratch_bytes(t, p, precision);
   });

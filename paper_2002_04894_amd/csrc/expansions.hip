@@ -769,7 +769,7 @@ bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, do
 // M2L on the matrix cores for p <= 15 (binary64, or binary32 on scaled
 // expansions for FMM_PREC_MIXED), else the binary64 kernel above
 void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, int prec, hipStream_t s) {
-  if (prec == FMM_PREC_MIXED ? launch_m2l_mfma_mixed(t, tb, Mx, Lx, s) : launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
+  if (prec != FMM_PREC_F64 ? launch_m2l_mfma_mixed(t, tb, Mx, Lx, s) : launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
   const int64_t nb = t.nbox_total - 1;  // levels 1..L
   k_m2l<<<(unsigned)nb, 64, 0, s>>>(t.view(), make_xt(tb), Mx, Lx);
   HIPCHECK(hipGetLastError());

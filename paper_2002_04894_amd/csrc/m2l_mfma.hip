@@ -58,6 +58,21 @@ struct Ar<float> {
   static constexpr int kRowStride = 20;
 };
 
+// Waves per SIMD the kernel is compiled for (the register budget per lane
+// is 512 / that).  binary64: 2 (its operand fragments already spill a little
+// at 256 registers).  binary32: 4 up to order 8, 3 above; measured on the
+// 2^24-point Plummer cloud at theta 0.6 against 2 waves: 131 / 137.6 / 159.3
+// ms at order 8, 156.6 / 175.2 ms (3 / 2 waves) at order 10, 220.5 / 232.5 at
+// 12, 232.2 / 259.6 at 13 (4 waves lost above order 8, on spills).
+template <int P, class R>
+struct Occ {
+  static constexpr int kWavesPerEu = 2;
+};
+template <int P>
+struct Occ<P, float> {
+  static constexpr int kWavesPerEu = P <= 8 ? 4 : 3;
+};
+
 // Orders this wave's LDS accesses around a point (other lanes of the wave
 // read what this lane wrote): a compiler barrier only, since the LDS unit
 // executes one wave's instructions in order.
@@ -554,10 +569,23 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
         wave_lds_fence();
         if (4 * r + 3 < NTW || 4 * r + (lane >> 4) < NTW) {
           const R* row = red + lane * C::RSTRIDE;
-          v2 v = *(const v2*)row;
+          if constexpr (MIXED) {
+            // the 16 binary32 pair results are summed in binary64 (exact for
+            // all but extreme exponent spreads)
+            double sum = 0.0;
 #pragma unroll
-          for (int k = 1; k < 8; ++k) v += *(const v2*)(row + 2 * k);
-          acc[r] += (double)(v.x + v.y);
+            for (int k = 0; k < 8; ++k) {
+              const v2 v = *(const v2*)(row + 2 * k);
+              sum += (double)v.x;
+              sum += (double)v.y;
+            }
+            acc[r] += sum;
+          } else {
+            v2 v = *(const v2*)row;
+#pragma unroll
+            for (int k = 1; k < 8; ++k) v += *(const v2*)(row + 2 * k);
+            acc[r] += (double)(v.x + v.y);
+          }
         }
         wave_lds_fence();
       }
@@ -583,7 +611,8 @@ __device__ __forceinline__ void m2l_wave(R* smem, const LevelView& lv, const R* 
 }
 
 template <int P, class R>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_m2l_mfma(
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(Occ<P, R>::kWavesPerEu,
+                                                                     Occ<P, R>::kWavesPerEu))) void k_m2l_mfma(
     LevelView lv, const R* __restrict__ mtab, const R* __restrict__ Mx, double* __restrict__ Lx,
     int64_t ntarget, const int32_t* __restrict__ order, int* __restrict__ queue) {
   __shared__ R smem[Cfg<P, R>::LDS];

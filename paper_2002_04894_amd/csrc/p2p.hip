@@ -131,6 +131,26 @@ __global__ void k_sum64(int64_t n, const int64_t* __restrict__ v, unsigned long 
 // The targets of leaf b are [tstart[b], tstart[b+1]) of (tx, ty, tz), written
 // to index tperm[.] of the outputs: the leaf's own sources (tstart = start,
 // tx = px, tperm = perm) or the separate targets grouped by leaf.
+// Binary32 near field (F32): coordinates are taken relative to the target
+// leaf's cell centre in binary64 and rounded to binary32, so that the
+// differences of nearby points keep binary32 accuracy; 1/r is the hardware
+// binary32 reciprocal square root; each lane sums the interactions of one
+// staged chunk in binary32 and adds the chunk sums into compensated binary32
+// accumulators (Kahan); the results are widened to binary64 before the far
+// field is added.  Two distinct points whose relative coordinates round to
+// the same binary32 values count as coincident (contribute nothing).
+struct Kahan {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ double get() const { return (double)s - (double)c; }
+};
+
+template <bool F32>
 __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restrict__ seg_leaf,
                                             const int64_t* __restrict__ seg_e0, const int64_t* __restrict__ leaf_seg,
                                             const int64_t* __restrict__ leaf_part, const int32_t* __restrict__ start,
@@ -143,8 +163,10 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restr
                                             const double* __restrict__ f1, const double* __restrict__ f2,
                                             const double* __restrict__ f3, double4* __restrict__ part,
                                             double* __restrict__ pot, double* __restrict__ ex,
-                                            double* __restrict__ ey, double* __restrict__ ez) {
-  __shared__ double4 buf[kP2PBuf];
+                                            double* __restrict__ ey, double* __restrict__ ez,
+                                            const double* __restrict__ lgeom) {
+  __shared__ double4 buf[F32 ? 1 : kP2PBuf];
+  __shared__ float4 bufs[F32 ? kP2PBuf : 1];
   const int64_t g = xcd_leaf(nseg);
   if (g >= nseg) return;
   const int lane = threadIdx.x;
@@ -158,6 +180,12 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restr
   const int TT = nt <= 16 ? 8 : (nt <= 32 ? 16 : (nt <= 64 ? 32 : 64));
   const int R = 64 / TT;
   const int tl = lane % TT, h = lane / TT;
+  double ccx = 0.0, ccy = 0.0, ccz = 0.0;  // binary32 mode: the target leaf's centre
+  if (F32) {
+    ccx = lgeom[b * 10 + 6];
+    ccy = lgeom[b * 10 + 7];
+    ccz = lgeom[b * 10 + 8];
+  }
   for (int c0 = t0; c0 < t1; c0 += 2 * TT) {
     const int ta = c0 + tl, tb = c0 + tl + TT;
     const bool va = ta < t1, vb = tb < t1;
@@ -166,6 +194,35 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restr
     const double xb = tx[ub], yb = ty[ub], zb = tz[ub];
     double fa = 0.0, gxa = 0.0, gya = 0.0, gza = 0.0;
     double fb = 0.0, gxb = 0.0, gyb = 0.0, gzb = 0.0;
+    // binary32: relative target coordinates, chunk sums, compensated totals
+    const float xfa = (float)(xa - ccx), yfa = (float)(ya - ccy), zfa = (float)(za - ccz);
+    const float xfb = (float)(xb - ccx), yfb = (float)(yb - ccy), zfb = (float)(zb - ccz);
+    float sa[4] = {0.f, 0.f, 0.f, 0.f}, sb[4] = {0.f, 0.f, 0.f, 0.f};
+    Kahan ka[4], kb[4];
+    auto interact32 = [&](const float4 s) {
+      {
+        const float dx = xfa - s.x, dy = yfa - s.y, dz = zfa - s.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+        const float qi = s.w * inv;
+        const float qi3 = qi * inv * inv;
+        sa[0] += qi;
+        sa[1] += qi3 * dx;
+        sa[2] += qi3 * dy;
+        sa[3] += qi3 * dz;
+      }
+      {
+        const float dx = xfb - s.x, dy = yfb - s.y, dz = zfb - s.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+        const float qi = s.w * inv;
+        const float qi3 = qi * inv * inv;
+        sb[0] += qi;
+        sb[1] += qi3 * dx;
+        sb[2] += qi3 * dy;
+        sb[3] += qi3 * dz;
+      }
+    };
     auto interact = [&](const double4 s) {
       {
         const double dx = xa - s.x, dy = ya - s.y, dz = za - s.z;
@@ -224,7 +281,13 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restr
 #pragma unroll
       for (int it = 0; it < kIt; ++it) {
         const int f = it * 64 + lane;
-        if (f < fill) buf[f] = v[it];
+        if (f < fill) {
+          if (F32)
+            bufs[f] = make_float4((float)(v[it].x - ccx), (float)(v[it].y - ccy), (float)(v[it].z - ccz),
+                                  (float)v[it].w);
+          else
+            buf[f] = v[it];
+        }
       }
       // entries staged completely, and how far into the next one
       int done = 0;
@@ -239,15 +302,43 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nseg, const int32_t* __restr
       e += done;
       __syncthreads();
       int u = h;
-      for (; u + 3 * R < fill; u += 4 * R) {
-        const double4 s0 = buf[u], s1 = buf[u + R], s2 = buf[u + 2 * R], s3 = buf[u + 3 * R];
-        interact(s0);
-        interact(s1);
-        interact(s2);
-        interact(s3);
+      if (F32) {
+        for (; u + 3 * R < fill; u += 4 * R) {
+          const float4 s0 = bufs[u], s1 = bufs[u + R], s2 = bufs[u + 2 * R], s3 = bufs[u + 3 * R];
+          interact32(s0);
+          interact32(s1);
+          interact32(s2);
+          interact32(s3);
+        }
+        for (; u < fill; u += R) interact32(bufs[u]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          ka[k].add(sa[k]);
+          kb[k].add(sb[k]);
+          sa[k] = 0.f;
+          sb[k] = 0.f;
+        }
+      } else {
+        for (; u + 3 * R < fill; u += 4 * R) {
+          const double4 s0 = buf[u], s1 = buf[u + R], s2 = buf[u + 2 * R], s3 = buf[u + 3 * R];
+          interact(s0);
+          interact(s1);
+          interact(s2);
+          interact(s3);
+        }
+        for (; u < fill; u += R) interact(buf[u]);
       }
-      for (; u < fill; u += R) interact(buf[u]);
       __syncthreads();
+    }
+    if (F32) {
+      fa = ka[0].get();
+      gxa = ka[1].get();
+      gya = ka[2].get();
+      gza = ka[3].get();
+      fb = kb[0].get();
+      gxb = kb[1].get();
+      gyb = kb[2].get();
+      gzb = kb[3].get();
     }
     // sum the source streams (fixed order)
 #pragma unroll
@@ -395,9 +486,10 @@ void p2p_plan(Tree& t, hipStream_t s) {
   dfree(acc, s);
 }
 
-// prec: FMM_PREC_F64, or FMM_PREC_MIXED for the binary32 M2L (the near field
-// stays in binary64: in binary32 its field lost up to 3e-5 relative on the
-// clustered workloads, through the cancellation among near contributions)
+// prec: FMM_PREC_F64; FMM_PREC_MIXED for the binary32 M2L; FMM_PREC_F32 for
+// the binary32 M2L and the binary32 near field (k_p2p<true>: its field loses
+// up to a few 1e-5 relative on clustered clouds, through the cancellation among
+// near contributions, so it serves loose tolerances only)
 namespace {
 
 // Upward and downward passes (Algorithm 1: P2M, M2M; Algorithm 3: M2L, L2L)
@@ -434,19 +526,25 @@ void far_field(const Tree& t, const double* qt, int p, int prec, const int32_t* 
 // (px, py, pz), plus the far field when far[0] is set; results go to index
 // perm[.] of the outputs.  leaf_part / npart: partial-sum layout of the split
 // leaves for these points.
-void near_field_and_store(const Tree& t, const double* qt, int parts, const int32_t* start, const double* px,
-                          const double* py, const double* pz, const int32_t* perm, const int64_t* leaf_part,
-                          int64_t npart, double* const far[4], double* pot, double* ex, double* ey, double* ez,
-                          hipStream_t s) {
+void near_field_and_store(const Tree& t, const double* qt, int parts, int prec, const int32_t* start,
+                          const double* px, const double* py, const double* pz, const int32_t* perm,
+                          const int64_t* leaf_part, int64_t npart, double* const far[4], double* pot, double* ex,
+                          double* ey, double* ez, hipStream_t s) {
   PhaseTimer& tm = timer();
   const Level& V = t.lev[t.L];
   tm.begin(FMM_PH_P2P, s);
   const unsigned gfin = (unsigned)((V.nbox + 3) / 4);
   if (parts & FMM_PART_NEAR) {
     double4* part = npart > 0 ? (double4*)dalloc(npart * sizeof(double4), s) : nullptr;
-    k_p2p<<<(unsigned)(8 * ((t.p2p_nseg + 7) / 8)), 64, 0, s>>>(
-        t.p2p_nseg, t.p2p_seg_leaf, t.p2p_seg_e0, t.p2p_leaf_seg, leaf_part, V.start, V.s_off, V.s_idx, t.px, t.py,
-        t.pz, qt, start, px, py, pz, perm, far[0], far[1], far[2], far[3], part, pot, ex, ey, ez);
+    const unsigned grid = (unsigned)(8 * ((t.p2p_nseg + 7) / 8));
+    if (prec == FMM_PREC_F32)
+      k_p2p<true><<<grid, 64, 0, s>>>(t.p2p_nseg, t.p2p_seg_leaf, t.p2p_seg_e0, t.p2p_leaf_seg, leaf_part, V.start,
+                                      V.s_off, V.s_idx, t.px, t.py, t.pz, qt, start, px, py, pz, perm, far[0], far[1],
+                                      far[2], far[3], part, pot, ex, ey, ez, V.geom);
+    else
+      k_p2p<false><<<grid, 64, 0, s>>>(t.p2p_nseg, t.p2p_seg_leaf, t.p2p_seg_e0, t.p2p_leaf_seg, leaf_part, V.start,
+                                       V.s_off, V.s_idx, t.px, t.py, t.pz, qt, start, px, py, pz, perm, far[0],
+                                       far[1], far[2], far[3], part, pot, ex, ey, ez, V.geom);
     HIPCHECK(hipGetLastError());
     if (part) {
       k_p2p_final<1><<<gfin, 256, 0, s>>>(V.nbox, start, t.p2p_leaf_seg, leaf_part, part, perm, far[0], far[1],
@@ -477,7 +575,7 @@ void evaluate(const Tree& t, const double* q, int p, int parts, int prec, double
   double* far[4] = {nullptr, nullptr, nullptr, nullptr};
   const Level& V = t.lev[t.L];
   if ((parts & FMM_PART_FAR) && t.L >= 1) far_field(t, qt, p, prec, V.start, t.px, t.py, t.pz, t.n, far, s);
-  near_field_and_store(t, qt, parts, V.start, t.px, t.py, t.pz, t.perm, t.p2p_leaf_part, t.p2p_npart, far, pot, ex,
+  near_field_and_store(t, qt, parts, prec, V.start, t.px, t.py, t.pz, t.perm, t.p2p_leaf_part, t.p2p_npart, far, pot, ex,
                        ey, ez, s);
   for (int k = 0; k < 4; ++k)
     if (far[k]) dfree(far[k], s);
@@ -495,7 +593,7 @@ size_t eval_scratch_bytes(const Tree& t, int p, int prec) {
     size_t expn = 0;
     if (t.L >= 1) {
       expn = 2 * nbox * stride * 8 + 256;                        // multipoles, locals, M2L queue
-      if (prec == FMM_PREC_MIXED && p <= tl::kMaxP) expn += nbox * stride * 4;  // binary32 multipoles
+      if (prec != FMM_PREC_F64 && p <= tl::kMaxP) expn += nbox * stride * 4;  // binary32 multipoles
     }
     const size_t part = (size_t)std::max<int64_t>(0, npart) * 32;
     return qt + far + std::max(expn, part);
@@ -513,7 +611,7 @@ void evaluate_targets(const Tree& t, const double* q, int p, int parts, int prec
   double* qt = gather_charges(t, q, s);
   double* far[4] = {nullptr, nullptr, nullptr, nullptr};
   if ((parts & FMM_PART_FAR) && t.L >= 1) far_field(t, qt, p, prec, t.tstart, t.tx, t.ty, t.tz, t.m, far, s);
-  near_field_and_store(t, qt, parts, t.tstart, t.tx, t.ty, t.tz, t.tperm, t.p2p_leaf_tpart, t.p2p_ntpart, far, pot,
+  near_field_and_store(t, qt, parts, prec, t.tstart, t.tx, t.ty, t.tz, t.tperm, t.p2p_leaf_tpart, t.p2p_ntpart, far, pot,
                        ex, ey, ez, s);
   for (int k = 0; k < 4; ++k)
     if (far[k]) dfree(far[k], s);

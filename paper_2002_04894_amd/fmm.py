@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
 FMM_PART_NEAR, FMM_PART_FAR, FMM_PART_ALL = 1, 2, 3
-FMM_PREC_F64, FMM_PREC_MIXED = 0, 1
+FMM_PREC_F64, FMM_PREC_MIXED, FMM_PREC_F32 = 0, 1, 2
 FMM_MAX_LEVELS, FMM_MAX_ORDER = 8, 20
 PHASES = ("tree", "lists", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 MAX_LEVELS, MAX_ORDER = 8, 20

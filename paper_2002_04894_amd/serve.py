@@ -125,6 +125,7 @@ class Tuner:
     kPointsPerLeaf = 40.0
     kSafety = 2.0
     kMixedMinTol = 1e-6  # mixed precision adds about 1e-7 relative error
+    kF32MinTol = 1e-4    # the binary32 near field adds up to a few 1e-5
 
     def __init__(self, theta: float = 0.5, errors: dict | None = None, cost: dict | None = None,
                  pmax: int = fmm.FMM_MAX_ORDER):
@@ -207,11 +208,16 @@ class Tuner:
         best = None
         for th in thetas:
             p = self.order(tol, L, th)
-            mixed = allow_mixed and tol >= self.kMixedMinTol and p <= 15
-            prec = fmm.FMM_PREC_MIXED if mixed else fmm.FMM_PREC_F64
-            key = (self._cost(L, th, prec, p), p, th)
-            if best is None or key < best[0]:
-                best = (key, (L, th, p, prec))
+            precs = [fmm.FMM_PREC_F64]
+            if allow_mixed and tol >= self.kMixedMinTol and p <= 15:
+                precs.append(fmm.FMM_PREC_MIXED)
+            if allow_mixed and tol >= self.kF32MinTol and p <= 15:
+                precs.append(fmm.FMM_PREC_F32)
+            # the lowest precision allowed unless a measured cost says otherwise
+            for prec in precs:
+                key = (self._cost(L, th, prec, p), p, th, -prec)
+                if best is None or key < best[0]:
+                    best = (key, (L, th, p, prec))
         return best[1]
 
     def calibrate(self, levels=(2, 3, 4), thetas=(0.4, 0.5), orders=range(1, 17), seed: int = 7,
@@ -236,7 +242,7 @@ class Tuner:
                 for th in thetas:
                     tree = fmm.fmm_build(*dev[:3], L, th, stream)
                     for p in orders:
-                        precs = [fmm.FMM_PREC_F64] + ([fmm.FMM_PREC_MIXED] if p <= 10 else [])
+                        precs = [fmm.FMM_PREC_F64] + ([fmm.FMM_PREC_MIXED, fmm.FMM_PREC_F32] if p <= 10 else [])
                         for prec in precs:
                             fmm.fmm_evaluate_tree(tree, dev[3], p, *out, stream, precision=prec)  # warm
                             ev0.record()

@@ -52,8 +52,9 @@ def test_tuner_rules():
     assert t.order(1e-8) == 18
     # unreachable accuracy: the largest order
     assert t.order(1e-30) == t.pmax
-    # mixed precision for 1e-6 and looser at p <= 15
-    assert t.choose(5000, 1e-4)[3] == 1 and t.choose(5000, 1e-8)[3] == 0
+    # without measured costs the lowest precision allowed: the binary32 near
+    # field for 1e-4 and looser, mixed precision for 1e-6, binary64 below
+    assert t.choose(5000, 1e-4)[3] == 2 and t.choose(5000, 1e-6)[3] == 1 and t.choose(5000, 1e-8)[3] == 0
     with pytest.raises(RuntimeError):
         serve.Tuner().order(1e-4)
 
@@ -220,7 +221,7 @@ def test_results_same_alone_and_in_the_mix():
     rng = np.random.default_rng(11)
     reqs = [serve.Request(i, 0.0, serve.DISTRIBUTIONS[i % 3], int(rng.integers(1000, 30_000)),
                           (1e-4, 1e-8)[i % 2], 5000 + i) for i in range(24)]
-    tuner = serve.Tuner(errors=SYNTH)  # p 5 (mixed) for 1e-4, p 18 (binary64) for 1e-8
+    tuner = serve.Tuner(errors=SYNTH)  # p 5 (binary32 near field) for 1e-4, p 18 (binary64) for 1e-8
     mixed = serve.Server(tuner, workers=6, keep_outputs=True).run(reqs, realtime=False)
     alone = serve.Server(tuner, workers=1, keep_outputs=True)
     stream = torch.cuda.Stream()
@@ -243,10 +244,11 @@ def _gpu():
 def test_served_results_match_the_oracle(orc):
     """Every served result against the CPU oracle at the parameters the tuner
     chose for it (same tree, lists and order): binary64 requests within
-    1e-12, mixed-precision ones within 1e-6 (the binary32 M2L), normwise over
+    1e-12, binary32-near-field ones (FMM_PREC_F32) within 1e-4, normwise over
     the points of sampled leaves.  Sizes lie on both sides of the chunked
-    bisection thresholds (8192, 16384); accuracies 1e-4 (mixed, p 5) and 1e-8
-    (binary64, p 18, the vector M2L) with the synthetic error table."""
+    bisection thresholds (8192, 16384); accuracies 1e-4 (binary32 near field,
+    p 5) and 1e-8 (binary64, p 18, the vector M2L) with the synthetic error
+    table."""
     torch = _gpu()
     sizes = [3000, 8100, 8300, 12000, 16300, 17000, 21000]
     reqs = [serve.Request(i, 0.0, serve.DISTRIBUTIONS[i % 3], n, tol, 7000 + i)
@@ -262,7 +264,7 @@ def test_served_results_match_the_oracle(orc):
         ref = t.evaluate(q, p, leaves=leaves)
         s, perm = t.start(L), t.perm()
         pts = np.concatenate([perm[s[b]:s[b + 1]] for b in leaves])
-        tol = 1e-12 if prec == 0 else 1e-6
+        tol = {0: 1e-12, 1: 1e-6, 2: 1e-4}[prec]
         print(f"[serve-oracle] rid {r.rid} n {r.n} L {L} theta {theta} p {p} prec {prec}", flush=True)
         for u, v in zip(got.outputs, ref):
             err = np.linalg.norm(u[pts] - v[pts]) / np.linalg.norm(v[pts])
