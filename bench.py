@@ -42,7 +42,14 @@ HBM_PEAK_GBS = 8000.0
 # entry holds only for the kernel source it was taken on (hash), else None.
 COPY_FETCH_SCALE = 1048576.0 / 524308.4375
 COPY_WRITE_SCALE = 1.0
-M2L_COUNTERS: dict = {}  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
+M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
+    # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12, mixed precision)
+    ("k_m2l_mfma<12, float>", 1 << 27, 0.6): {
+        "sources_sha256": "6c7a3dc22f998d7dfa03e6a33dd6c67674e19006a7a6f8951c30558036a21105",
+        "fetch_kib": 3976526450.0625,
+        "write_kib": 5469789.375,
+    },
+}
 
 
 def m2l_sources_sha256() -> str:
@@ -422,7 +429,7 @@ def copy_probe(nbytes: int):
     print(json.dumps({"copy_bytes": a.numel() * 8}), flush=True)
 
 
-def cpu_baseline(w, theta: float, p: int, ns: int = 1 << 15) -> dict:
+def cpu_baseline(w, theta: float, p: int, ns: int = 1 << 18) -> dict:
     """The CPU oracle as it stands (binary64, the paper's rotational M2L,
     OpenMP threads over boxes and leaves on every host core) timed on a
     bounded sample of the same workload: the same generator with `ns` points
