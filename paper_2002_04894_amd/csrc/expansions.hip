@@ -288,6 +288,25 @@ HostTables make_host_tables(int p) {
   return h;
 }
 
+// J (or J^T) of every degree as binary32, its vanishing entries (between the
+// two parity classes) left out, in the order the vector M2L kernel uses them:
+// per degree, class 0 then class 1, row by row, columns ascending
+std::vector<float> compact_j(const HostTables& h, int p, bool trans) {
+  std::vector<float> out;
+  for (int n = 0; n <= p; ++n) {
+    const int sd = 2 * n + 1;
+    for (int cls = 0; cls < 2; ++cls)
+      for (int i = 0; i < sd; ++i) {
+        if (parity_class(i) != cls) continue;
+        for (int q = 0; q < sd; ++q) {
+          if (parity_class(q) != cls) continue;
+          out.push_back((float)(trans ? h.J[h.joff[n] + q * sd + i] : h.J[h.joff[n] + i * sd + q]));
+        }
+      }
+  }
+  return out;
+}
+
 std::mutex g_tab_mu;
 std::map<std::pair<int, int>, Tables> g_tabs;  // (device, p) -> tables
 
@@ -341,6 +360,10 @@ const Tables& tables_for(int p, hipStream_t s) {
     t.mtab = upload(h.mtab, s);
     t.mtab32 = upload(h.mtab32, s);
     t.sdeg = upload(h.sdeg, s);
+    std::vector<float> a32(h.A.begin(), h.A.end());
+    t.J32 = upload(compact_j(h, p, false), s);
+    t.JT32 = upload(compact_j(h, p, true), s);
+    t.A32 = upload(a32, s);
   }
   HIPCHECK(hipStreamSynchronize(s));  // also keeps h alive until the copies are done
   return g_tabs.emplace(std::make_pair(dev, p), t).first->second;
