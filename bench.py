@@ -32,6 +32,7 @@ from paper_2002_04894_amd import fmm, workloads  # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6        # MI355X binary64 vector (and matrix) peak
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X binary32 matrix peak (dense)
+LANE_M2L_MAX_P = 14            # mixed precision: the per-lane M2L kernel up to this order, 16x16 tiles above
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one M2L launch, per kernel and workload: from two rocprofv3
@@ -52,10 +53,11 @@ M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", 
 }
 
 
-def m2l_sources_sha256() -> str:
+def m2l_sources_sha256(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("m2l_mfma.hip", "tile_layout.h"):
+    for f in (("m2l_lane.hip", "lane_ops.h") if kernel.startswith("k_m2l_lane") else ("m2l_mfma.hip",)) + (
+            "tile_layout.h",):
         with open(os.path.join(ROOT, "paper_2002_04894_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -65,7 +67,7 @@ def m2l_traffic_gb(kernel: str, n: int, theta: float):
     """HBM bytes (GB) per M2L launch from the counters above, or None when
     none were taken for this kernel, workload and kernel source."""
     c = M2L_COUNTERS.get((kernel, n, theta))
-    if c is None or m2l_sources_sha256() != c["sources_sha256"]:
+    if c is None or m2l_sources_sha256(kernel) != c["sources_sha256"]:
         return None
     kib = c["fetch_kib"] * COPY_FETCH_SCALE + c["write_kib"] * COPY_WRITE_SCALE
     return round(kib * 1024 / 1e9, 2)
@@ -235,7 +237,9 @@ def timed_leg(X, Y, Z, Q, L, theta, p, prec, outs, steps, warmup, stream, torch)
     m2l_ms = phase_avg["m2l"]
     achieved = m2l_pairs * m2l_flops_per_pair(p) / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0
     mixed = prec == fmm.FMM_PREC_MIXED and p <= 15
-    if p <= 15:
+    if mixed and p <= LANE_M2L_MAX_P:
+        kernel, bound, peak = f"k_m2l_lane<{p}>", "mfma", FP32_MFMA_PEAK_TFLOPS
+    elif p <= 15:
         kernel = f"k_m2l_mfma<{p}, {'float' if mixed else 'double'}>"
         bound, peak = "mfma", FP32_MFMA_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
     else:

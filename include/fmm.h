@@ -131,8 +131,9 @@ fmm_status fmm_evaluate_tree_parts(fmm_tree* tree, const double* q, int p, int p
  * evaluates the dominant M2L step (Section 2.1.3) in binary32 for orders
  * p <= 15: the multipoles are scaled by powers of their box radius, so that
  * every translation factor (r_source/rho)^n, (r_target/rho)^j is below one;
- * the rotations and the z-axis translation run on the binary32 matrix cores;
- * the 16 pair results of a batch and the batches are summed in binary64;
+ * the rotations and the z-axis translation run on the binary32 matrix cores
+ * (one pair per lane up to order 14, 16-pair tiles at order 15); the pair
+ * results of a batch are summed in binary32 and the batches in binary64;
  * the local expansions are unscaled into binary64.  The tree, P2M, M2M, L2L,
  * L2P and the near field (P2P) stay in binary64, as do all final sums.  The
  * far field then differs from the binary64 one by about 1e-7 relative

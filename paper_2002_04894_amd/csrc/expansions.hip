@@ -34,6 +34,7 @@
 
 #include "fmm_internal.h"
 #include "tile_layout.h"
+#include "lane_ops.h"
 
 namespace fmm {
 
@@ -288,21 +289,43 @@ HostTables make_host_tables(int p) {
   return h;
 }
 
-// J (or J^T) of every degree as binary32, its vanishing entries (between the
-// two parity classes) left out, in the order the vector M2L kernel uses them:
-// per degree, class 0 then class 1, row by row, columns ascending
-std::vector<float> compact_j(const HostTables& h, int p, bool trans) {
-  std::vector<float> out;
-  for (int n = 0; n <= p; ++n) {
-    const int sd = 2 * n + 1;
-    for (int cls = 0; cls < 2; ++cls)
-      for (int i = 0; i < sd; ++i) {
-        if (parity_class(i) != cls) continue;
-        for (int q = 0; q < sd; ++q) {
-          if (parity_class(q) != cls) continue;
-          out.push_back((float)(trans ? h.J[h.joff[n] + q * sd + i] : h.J[h.joff[n] + i * sd + q]));
-        }
+// The operands of the per-lane M2L kernel on the 4x4x1 matrix instruction, in
+// the order of lane_ops.h: J, J^T and the z-translation core, each as whole
+// groups of 64 values.
+std::vector<float> lane_tables(const HostTables& h, int p) {
+  using namespace lops;
+  std::vector<float> out((size_t)table_floats(p), 0.0f);
+  size_t base = 0;
+  for (int trans = 0; trans < 2; ++trans) {
+    int u = 0;
+    for (int n = 0; n <= p; ++n) {
+      const int sd = 2 * n + 1;
+      for (int cls = 0; cls < 2; ++cls) {
+        const int s = cls_size(n, cls);
+        for (int k = 0; k < s; ++k)
+          for (int c = 0; c < chunks(s); ++c, ++u)
+            for (int i = 0; i < 4; ++i) {
+              const int r = 4 * c + i;
+              if (r >= s) continue;
+              const int a = cls_member(n, cls, r), b = cls_member(n, cls, k);
+              const double v = trans ? h.J[h.joff[n] + b * sd + a] : h.J[h.joff[n] + a * sd + b];
+              out[base + (size_t)(u / 16) * 64 + 4 * (u % 16) + i] = (float)v;
+            }
       }
+    }
+    base += (size_t)64 * groups(n_j(p));
+  }
+  const int P1 = p + 1;
+  int u = 0;
+  for (int m = 0; m <= p; ++m) {
+    const int s = p + 1 - m;
+    for (int k = 0; k < s; ++k)
+      for (int c = 0; c < chunks(s); ++c, ++u)
+        for (int i = 0; i < 4; ++i) {
+          const int r = 4 * c + i;
+          if (r >= s) continue;
+          out[base + (size_t)(u / 16) * 64 + 4 * (u % 16) + i] = (float)h.A[((size_t)m * P1 + m + r) * P1 + m + k];
+        }
   }
   return out;
 }
@@ -360,10 +383,7 @@ const Tables& tables_for(int p, hipStream_t s) {
     t.mtab = upload(h.mtab, s);
     t.mtab32 = upload(h.mtab32, s);
     t.sdeg = upload(h.sdeg, s);
-    std::vector<float> a32(h.A.begin(), h.A.end());
-    t.J32 = upload(compact_j(h, p, false), s);
-    t.JT32 = upload(compact_j(h, p, true), s);
-    t.A32 = upload(a32, s);
+    t.lane = upload(lane_tables(h, p), s);
   }
   HIPCHECK(hipStreamSynchronize(s));  // also keeps h alive until the copies are done
   return g_tabs.emplace(std::make_pair(dev, p), t).first->second;

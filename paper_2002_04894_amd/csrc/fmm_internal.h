@@ -150,11 +150,9 @@ struct Tables {
   double* mtab = nullptr;
   float* mtab32 = nullptr;  // the same in binary32, rows ordered for the binary32 MFMA
   int8_t* sdeg = nullptr;  // degree of each storage position, -1 for a zero slot
-  // binary32 operands of the vector M2L kernel (m2l_valu.hip): the nonzero
-  // entries of J and of J^T in the order that kernel uses them, and A
-  float* J32 = nullptr;
-  float* JT32 = nullptr;
-  float* A32 = nullptr;
+  // J, J^T and the z-translation core as operands of the per-lane M2L
+  // kernel's 4x4x1 matrix instructions (lane_ops.h), binary32
+  float* lane = nullptr;
   bool tiled = false;
 };
 const Tables& tables_for(int p, hipStream_t s);

@@ -1,0 +1,58 @@
+// Operand order of the per-lane M2L kernel (m2l_lane.hip) on the 16-block
+// 4x4x1 matrix instruction, shared by the kernel and by the host code that
+// packs its operator tables.
+//
+// Each lane holds one pair's expansion; a fixed operator block B (s x s) acts
+// on s of the lane's coefficients as a sequence of instructions, one per
+// (input column k, output chunk c of 4 rows): D_c += B[4c .. 4c+3][k] * x_k.
+// The 4 operator values of an instruction are the A operand of one block,
+// broadcast to all 16 blocks, so 16 consecutive instructions take theirs from
+// one register: the table holds, per group of 16 instructions, 64 values,
+// value 4 * (u mod 16) + i = row i of instruction u (zero past the block).
+//
+// Blocks, in order:
+//   J or J^T: per degree n, per parity class cls (0: n+1 members, 1: n), the
+//             class members in standard order (the quarter turn about x
+//             keeps the classes apart);
+//   z core:   per order m, rows d and columns n = m .. P (one table for the
+//             cosine and the sine parts, which share it).
+#pragma once
+
+namespace fmm {
+namespace lops {
+
+// 0 / 1: the two classes of the standard index i within a degree (c_m at
+// i = 2m-1, s_m at i = 2m) that the quarter turn about x keeps apart
+__host__ __device__ constexpr int parity_cls(int i) {
+  return i == 0 ? 0 : ((((i + 1) >> 1) + ((i & 1) ? 0 : 1)) & 1);
+}
+__host__ __device__ constexpr int cls_size(int n, int cls) { return cls == 0 ? n + 1 : n; }
+// r-th member (standard index within degree n) of class cls
+__host__ __device__ constexpr int cls_member(int n, int cls, int r) {
+  for (int i = 0; i < 2 * n + 1; ++i)
+    if (parity_cls(i) == cls && r-- == 0) return i;
+  return -1;
+}
+__host__ __device__ constexpr int chunks(int s) { return (s + 3) / 4; }
+// first instruction of block (n, cls) of a J application, and of order m of
+// the z translation at expansion order p (its blocks have p + 1 - m rows)
+__host__ __device__ constexpr int j_offset(int n, int cls) {
+  int u = 0;
+  for (int a = 0; a < n; ++a)
+    for (int c = 0; c < 2; ++c) u += cls_size(a, c) * chunks(cls_size(a, c));
+  return cls == 0 ? u : u + cls_size(n, 0) * chunks(cls_size(n, 0));
+}
+__host__ __device__ constexpr int z_offset(int p, int m) {
+  int u = 0;
+  for (int a = 0; a < m; ++a) u += (p + 1 - a) * chunks(p + 1 - a);
+  return u;
+}
+// instructions of one J application and of the z translation (per part)
+__host__ __device__ constexpr int n_j(int p) { return j_offset(p + 1, 0); }
+__host__ __device__ constexpr int n_z(int p) { return z_offset(p, p + 1); }
+__host__ __device__ constexpr int groups(int u) { return (u + 15) / 16; }
+// table floats: J, J^T, z core, each padded to whole groups
+__host__ __device__ constexpr int table_floats(int p) { return 64 * (2 * groups(n_j(p)) + groups(n_z(p))); }
+
+}  // namespace lops
+}  // namespace fmm

@@ -706,7 +706,7 @@ bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* 
   return launch_any<double>(t, tb, Mx, Lx, s);
 }
 
-bool launch_m2l_valu32(const Tree& t, const Tables& tb, const float* Mf, double* Lx, hipStream_t s);
+bool launch_m2l_lane32(const Tree& t, const Tables& tb, const float* Mf, double* Lx, hipStream_t s);
 
 bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   if (!tb.tiled) return false;
@@ -716,8 +716,8 @@ bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, do
                                                                       t.nbox_total);
     HIPCHECK(hipGetLastError());
   }
-  // orders up to 9 on the vector units (no tile padding), above on the matrix cores
-  const bool ok = launch_m2l_valu32(t, tb, Mf, Lx, s) || launch_any<float>(t, tb, Mf, Lx, s);
+  // orders up to 14 one pair per lane (m2l_lane.hip), 15 in 16x16 tiles
+  const bool ok = launch_m2l_lane32(t, tb, Mf, Lx, s) || launch_any<float>(t, tb, Mf, Lx, s);
   dfree(Mf, s);
   return ok;
 }
