@@ -41,29 +41,9 @@ __host__ __device__ constexpr int deg_of(int k) {
 }
 // index of c_{n,m} (t = 0) or s_{n,m} (t = 1) in the standard order
 __host__ __device__ constexpr int cidx(int n, int m, int t) { return n * n + (m == 0 ? 0 : 2 * m - 1 + t); }
-// storage position of standard index k in the tile layout of order P
-template <int P>
-__host__ __device__ constexpr int tpos(int k) {
-  const int n = deg_of(k), i = k - n * n, m = (i + 1) >> 1, sine = (i != 0 && (i & 1) == 0) ? 1 : 0;
-  for (int t = 0; t < tl::ntiles(P); ++t)
-    for (int s = 0; s < 16; ++s) {
-      const tl::Slot d = tl::decode(P, t, s);
-      if (d.valid && d.n == n && d.m == m && d.sine == sine) return tl::spos(t, s);
-    }
-  return -1;
-}
-// the whole map, built at compile time (indexing a constant table keeps the
-// expansion in registers after unrolling)
-template <int P>
-struct PosTab {
-  int v[(P + 1) * (P + 1)];
-};
-template <int P>
-__host__ __device__ constexpr PosTab<P> make_pos() {
-  PosTab<P> t{};
-  for (int k = 0; k < (P + 1) * (P + 1); ++k) t.v[k] = tpos<P>(k);
-  return t;
-}
+// floats per box of the binary32 multipoles this kernel reads: the (P+1)^2
+// coefficients in the standard order, padded to whole 16-byte loads
+__host__ __device__ constexpr int dense_stride(int p) { return ((p + 1) * (p + 1) + 3) & ~3; }
 
 // sizes of the halving exchanges: level 0 holds all NT values, each of the
 // six levels keeps the lane's half (rounded up)
@@ -253,10 +233,11 @@ struct LaneCfg {
 // Persistent waves: each takes the next target of the longest-first order.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LaneCfg<P>::kWaves, LaneCfg<P>::kWaves))) void
-k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__ pos, const float* __restrict__ Mx,
+k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__ pos, const float* __restrict__ Mf,
            double* __restrict__ Lx, int64_t ntarget, const int32_t* __restrict__ order, int* __restrict__ queue) {
   constexpr int NT = (P + 1) * (P + 1);
   constexpr int S = tl::stride(P);
+  constexpr int SD = dense_stride(P);
   constexpr int NF = lvl(NT, 6);  // values a lane holds after the exchanges
   constexpr bool FR = LaneCfg<P>::kFresh;
   constexpr int GJ = 64 * lops::groups(lops::n_j(P));  // table: J, J^T, z core
@@ -277,7 +258,7 @@ k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__
     const double rt = geo[bi * 10 + 9] > 0.0 ? geo[bi * 10 + 9] : 1.0;
     const int64_t e0 = lv.w_off[l][bi], e1 = lv.w_off[l][bi + 1];
     const int32_t* widx = lv.w_idx[l];
-    const float* Mlev = Mx + (size_t)lv.gofs[l] * S;
+    const float* Mlev = Mf + (size_t)lv.gofs[l] * SD;
     double acc[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) acc[i] = 0.0;
@@ -299,11 +280,15 @@ k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__
       const float out_mult = valid ? (float)irho : 0.f;
 
       float X[NT];
-      const float* src = Mlev + (size_t)j * S;
-      constexpr PosTab<P> kPos = make_pos<P>();
-      static_assert(kPos.v[0] >= 0, "tile layout map");
+      const float4* src = (const float4*)(Mlev + (size_t)j * SD);
 #pragma unroll
-      for (int k = 0; k < NT; ++k) X[k] = src[kPos.v[k]];
+      for (int q = 0; q < SD / 4; ++q) {
+        const float4 v = src[q];
+        if (4 * q + 0 < NT) X[4 * q + 0] = v.x;
+        if (4 * q + 1 < NT) X[4 * q + 1] = v.y;
+        if (4 * q + 2 < NT) X[4 * q + 2] = v.z;
+        if (4 * q + 3 < NT) X[4 * q + 3] = v.w;
+      }
 
       // the steps are kept apart in the schedule (interleaving them only
       // raises the number of live values)
@@ -376,13 +361,43 @@ k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__
   }
 }
 
+// The binary32 multipoles of levels 1..L for this kernel, from the binary64
+// ones (tile layout, S per box): standard order, scaled by r^-n (r the box
+// radius, 1 for a box of zero extent; the same products as for the tile
+// kernel's copy), dense_stride(P) floats per box with a zero tail.
+template <int P>
+__global__ void k_scale_lane(LevelView lv, int S, const int* __restrict__ pos, const double* __restrict__ Mx,
+                             float* __restrict__ Mf, int64_t nbox_total) {
+  constexpr int NT = (P + 1) * (P + 1), SD = dense_stride(P);
+  const int64_t gid = 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gid >= nbox_total) return;
+  int l = 1;
+  while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
+  const double r = lv.geom[l][(gid - lv.gofs[l]) * 10 + 9];
+  const double is = r > 0.0 ? 1.0 / r : 1.0;
+  for (int k = threadIdx.x & 63; k < SD; k += 64) {
+    float v = 0.f;
+    if (k < NT) {
+      const int n = deg_of(k);
+      double d = Mx[(size_t)gid * S + pos[k]];
+      for (int q = 0; q < n; ++q) d *= is;
+      v = (float)d;
+    }
+    Mf[(size_t)gid * SD + k] = v;
+  }
+}
+
 __global__ void k_zero_queue_l(int* queue) {
   if (threadIdx.x == 0) *queue = 0;
 }
 
 template <int P>
-void launch_one_lane(const Tree& t, const Tables& tb, const float* Mf, double* Lx, hipStream_t s) {
+void launch_one_lane(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   const int64_t ntarget = t.nbox_total - 1;
+  if (ntarget <= 0) return;
+  float* Mf = (float*)dalloc((size_t)t.nbox_total * dense_stride(P) * sizeof(float), s);
+  k_scale_lane<P><<<(unsigned)((ntarget + 3) / 4), 256, 0, s>>>(t.view(), tb.stride, tb.pos, Mx, Mf, t.nbox_total);
+  HIPCHECK(hipGetLastError());
   static const int grid_max = [] {
     int dev = 0, ncu = 0, per = 0;
     HIPCHECK(hipGetDevice(&dev));
@@ -398,29 +413,30 @@ void launch_one_lane(const Tree& t, const Tables& tb, const float* Mf, double* L
   k_m2l_lane<P><<<grid, 256, 0, s>>>(t.view(), tb.lane, tb.pos, Mf, Lx, ntarget, t.m2l_order, queue);
   HIPCHECK(hipGetLastError());
   dfree(queue, s);
+  dfree(Mf, s);
 }
 
 }  // namespace
 
-// the per-lane kernel for the scaled binary32 multipoles Mf (tile layout);
-// false above order 14, where the 16x16 tile kernel is as fast
-bool launch_m2l_lane32(const Tree& t, const Tables& tb, const float* Mf, double* Lx, hipStream_t s) {
+// mixed-precision M2L with this kernel from the binary64 multipoles Mx (tile
+// layout); false above order 14, where the 16x16 tile kernel is as fast
+bool launch_m2l_lane32(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   switch (tb.p) {
-    case 0: launch_one_lane<0>(t, tb, Mf, Lx, s); break;
-    case 1: launch_one_lane<1>(t, tb, Mf, Lx, s); break;
-    case 2: launch_one_lane<2>(t, tb, Mf, Lx, s); break;
-    case 3: launch_one_lane<3>(t, tb, Mf, Lx, s); break;
-    case 4: launch_one_lane<4>(t, tb, Mf, Lx, s); break;
-    case 5: launch_one_lane<5>(t, tb, Mf, Lx, s); break;
-    case 6: launch_one_lane<6>(t, tb, Mf, Lx, s); break;
-    case 7: launch_one_lane<7>(t, tb, Mf, Lx, s); break;
-    case 8: launch_one_lane<8>(t, tb, Mf, Lx, s); break;
-    case 9: launch_one_lane<9>(t, tb, Mf, Lx, s); break;
-    case 10: launch_one_lane<10>(t, tb, Mf, Lx, s); break;
-    case 11: launch_one_lane<11>(t, tb, Mf, Lx, s); break;
-    case 12: launch_one_lane<12>(t, tb, Mf, Lx, s); break;
-    case 13: launch_one_lane<13>(t, tb, Mf, Lx, s); break;
-    case 14: launch_one_lane<14>(t, tb, Mf, Lx, s); break;
+    case 0: launch_one_lane<0>(t, tb, Mx, Lx, s); break;
+    case 1: launch_one_lane<1>(t, tb, Mx, Lx, s); break;
+    case 2: launch_one_lane<2>(t, tb, Mx, Lx, s); break;
+    case 3: launch_one_lane<3>(t, tb, Mx, Lx, s); break;
+    case 4: launch_one_lane<4>(t, tb, Mx, Lx, s); break;
+    case 5: launch_one_lane<5>(t, tb, Mx, Lx, s); break;
+    case 6: launch_one_lane<6>(t, tb, Mx, Lx, s); break;
+    case 7: launch_one_lane<7>(t, tb, Mx, Lx, s); break;
+    case 8: launch_one_lane<8>(t, tb, Mx, Lx, s); break;
+    case 9: launch_one_lane<9>(t, tb, Mx, Lx, s); break;
+    case 10: launch_one_lane<10>(t, tb, Mx, Lx, s); break;
+    case 11: launch_one_lane<11>(t, tb, Mx, Lx, s); break;
+    case 12: launch_one_lane<12>(t, tb, Mx, Lx, s); break;
+    case 13: launch_one_lane<13>(t, tb, Mx, Lx, s); break;
+    case 14: launch_one_lane<14>(t, tb, Mx, Lx, s); break;
     default: return false;
   }
   return true;

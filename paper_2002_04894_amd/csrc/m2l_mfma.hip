@@ -706,18 +706,19 @@ bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* 
   return launch_any<double>(t, tb, Mx, Lx, s);
 }
 
-bool launch_m2l_lane32(const Tree& t, const Tables& tb, const float* Mf, double* Lx, hipStream_t s);
+bool launch_m2l_lane32(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
 
 bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   if (!tb.tiled) return false;
+  // orders up to 14 one pair per lane (m2l_lane.hip), 15 in 16x16 tiles
+  if (launch_m2l_lane32(t, tb, Mx, Lx, s)) return true;
   float* Mf = (float*)dalloc((size_t)t.nbox_total * tb.stride * sizeof(float), s);
   if (t.nbox_total > 1) {
     k_scale_m32<<<(unsigned)((t.nbox_total - 1 + 3) / 4), 256, 0, s>>>(t.view(), tb.stride, tb.sdeg, Mx, Mf,
                                                                       t.nbox_total);
     HIPCHECK(hipGetLastError());
   }
-  // orders up to 14 one pair per lane (m2l_lane.hip), 15 in 16x16 tiles
-  const bool ok = launch_m2l_lane32(t, tb, Mf, Lx, s) || launch_any<float>(t, tb, Mf, Lx, s);
+  const bool ok = launch_any<float>(t, tb, Mf, Lx, s);
   dfree(Mf, s);
   return ok;
 }
