@@ -45,10 +45,10 @@ COPY_FETCH_SCALE = 1048576.0 / 524308.4375
 COPY_WRITE_SCALE = 1.0
 M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
     # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12, mixed precision)
-    ("k_m2l_mfma<12, float>", 1 << 27, 0.6): {
-        "sources_sha256": "6c7a3dc22f998d7dfa03e6a33dd6c67674e19006a7a6f8951c30558036a21105",
-        "fetch_kib": 3976526450.0625,
-        "write_kib": 5469789.375,
+    ("k_m2l_lane<12>", 1 << 27, 0.6): {
+        "sources_sha256": "a2295f4a9a3f178d7bda493cb329aff43a8237a6b32dbbd8f7377b103189b8a6",
+        "fetch_kib": 4279972417.8125,
+        "write_kib": 635745128.6875,
     },
 }
 
