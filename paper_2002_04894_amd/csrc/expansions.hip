@@ -330,6 +330,36 @@ std::vector<float> lane_tables(const HostTables& h, int p) {
   return out;
 }
 
+// The operands of the binary64 per-quad M2L kernel (lane_ops.h): J and J^T
+// as 4x4 parts in instruction order, then the z-translation core.
+std::vector<double> quad_tables(const HostTables& h, int p) {
+  using namespace lops;
+  std::vector<double> out((size_t)qtable_doubles(p), 0.0);
+  for (int trans = 0; trans < 2; ++trans) {
+    double* T = out.data() + (size_t)trans * 16 * qj_count(p);
+    for (int d = 0; d <= p; ++d) {
+      const int sd = 2 * d + 1, nr = qreg(d);
+      for (int x = 0; x < 2; ++x)
+        for (int g = 0; g < nr; ++g)
+          for (int c = 0; c < nr; ++c) {
+            const int u = qj_offset(d, x) + g * nr + c;
+            for (int k = 0; k < 4; ++k)
+              for (int i = 0; i < 4; ++i) {
+                const int a = qmember(d, x, 4 * c + i), b = qmember(d, x, 4 * g + k);
+                if (a < 0 || b < 0) continue;
+                T[16 * u + 4 * k + i] = trans ? h.J[h.joff[d] + b * sd + a] : h.J[h.joff[d] + a * sd + b];
+              }
+          }
+    }
+  }
+  double* Z = out.data() + (size_t)2 * 16 * qj_count(p);
+  const size_t P1 = (size_t)p + 1;
+  for (int m = 0; m <= p; ++m)
+    for (int d = m; d <= p; ++d)
+      for (int n = m; n <= p; ++n) Z[((size_t)m * P1 + d) * P1 + n] = h.A[((size_t)m * P1 + d) * P1 + n];
+  return out;
+}
+
 std::mutex g_tab_mu;
 std::map<std::pair<int, int>, Tables> g_tabs;  // (device, p) -> tables
 
@@ -379,6 +409,7 @@ const Tables& tables_for(int p, hipStream_t s) {
   t.pos = upload(h.pos, s);
   t.ipos = upload(h.ipos, s);
   t.tiled = h.tiled;
+  t.quad = upload(quad_tables(h, p), s);
   if (h.tiled) {
     t.mtab = upload(h.mtab, s);
     t.mtab32 = upload(h.mtab32, s);
@@ -808,12 +839,18 @@ void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t 
 }
 bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
 bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
+bool launch_m2l_quad64(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
 
 // M2L on the matrix cores for p <= 15 (binary64, or binary32 on scaled
 // expansions for FMM_PREC_MIXED), else the binary64 kernel above
 void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, int prec, hipStream_t s) {
-  if (prec != FMM_PREC_F64 ? launch_m2l_mfma_mixed(t, tb, Mx, Lx, s) : launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
-  const int64_t nb = t.nbox_total - 1;  // levels 1..L
+  // binary32 (orders up to 15), else binary64: four lanes per pair on the
+  // matrix cores (orders up to 13 and 16..18), 16-pair tiles (14, 15), the
+  // vector kernel above
+  if (prec != FMM_PREC_F64 && launch_m2l_mfma_mixed(t, tb, Mx, Lx, s)) return;
+  if (launch_m2l_quad64(t, tb, Mx, Lx, s)) return;
+  if (launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
+  const int64_t nb = t.nbox_total - 1;
   k_m2l<<<(unsigned)nb, 64, 0, s>>>(t.view(), make_xt(tb), Mx, Lx);
   HIPCHECK(hipGetLastError());
 }

@@ -153,6 +153,9 @@ struct Tables {
   // J, J^T and the z-translation core as operands of the per-lane M2L
   // kernel's 4x4x1 matrix instructions (lane_ops.h), binary32
   float* lane = nullptr;
+  // J, J^T and the z-translation core for the binary64 per-quad M2L kernel
+  // (lane_ops.h)
+  double* quad = nullptr;
   bool tiled = false;
 };
 const Tables& tables_for(int p, hipStream_t s);

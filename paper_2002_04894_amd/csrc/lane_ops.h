@@ -51,8 +51,51 @@ __host__ __device__ constexpr int z_offset(int p, int m) {
 __host__ __device__ constexpr int n_j(int p) { return j_offset(p + 1, 0); }
 __host__ __device__ constexpr int n_z(int p) { return z_offset(p, p + 1); }
 __host__ __device__ constexpr int groups(int u) { return (u + 15) / 16; }
+// floats per box of the binary32 multipoles the per-lane kernel reads: the
+// (p+1)^2 coefficients in the standard order, padded to whole 16-byte loads
+__host__ __device__ constexpr int dense_stride(int p) { return ((p + 1) * (p + 1) + 3) & ~3; }
 // table floats: J, J^T, z core, each padded to whole groups
 __host__ __device__ constexpr int table_floats(int p) { return 64 * (2 * groups(n_j(p)) + groups(n_z(p))); }
+
+// ---- the binary64 per-quad M2L kernel (m2l_quad.hip) on v_mfma_f64_4x4x4f64 ----
+//
+// A wave takes 16 pairs; lane 16 k + q holds phase k (0..3) of pair q.  Per
+// degree d the coefficients form two blocks indexed by the order m = 0..d:
+// block 0 holds c_m for even m and s_m for odd m, block 1 the others (its
+// member 0, s_0, is a zero slot) -- the two classes that the quarter turn
+// about x keeps apart, ordered by m.  Member m of a block sits in phase
+// m mod 4, register m / 4 of the block, so that the cosine and sine parts of
+// (d, m) share a lane and register index, and all degrees of order m share a
+// lane.  A block product takes ceil((d+1)/4)^2 instructions, one per (k-step
+// g, output chunk c): D_c += Op[4c .. 4c+3][4g .. 4g+3] X_g; the operand of
+// instruction u is 16 values, row i and column k of its 4x4 part at 16 u +
+// 4 k + i (the lane layout of the instruction: lane 16 k + 4 b + i holds
+// A[i][k] of block b, for every b).
+__host__ __device__ constexpr int qreg(int d) { return d / 4 + 1; }
+// first register of block (d, x)
+__host__ __device__ constexpr int qbase(int d, int x) {
+  int r = 0;
+  for (int a = 0; a < d; ++a) r += 2 * qreg(a);
+  return r + x * qreg(d);
+}
+__host__ __device__ constexpr int nq(int p) { return qbase(p + 1, 0); }
+// standard index within degree d of member m of block x, or -1 for a zero slot
+__host__ __device__ constexpr int qmember(int d, int x, int m) {
+  if (m > d) return -1;
+  if ((m & 1) == x) return m == 0 ? 0 : 2 * m - 1;  // c_m
+  return m == 0 ? -1 : 2 * m;                       // s_m
+}
+// first instruction of block (d, x) in one J application
+__host__ __device__ constexpr int qj_offset(int d, int x) {
+  int u = 0;
+  for (int a = 0; a < d; ++a) u += 2 * qreg(a) * qreg(a);
+  return u + x * qreg(d) * qreg(d);
+}
+__host__ __device__ constexpr int qj_count(int p) { return qj_offset(p + 1, 0); }
+// table: J, J^T (16 values per instruction each), then the z-translation core
+// A[m][d][n] for m = 0 .. p + 1 (order p + 1 all zero: the slot of the lanes
+// whose order exceeds p)
+__host__ __device__ constexpr int qtable_doubles(int p) { return 2 * 16 * qj_count(p) + (p + 2) * (p + 1) * (p + 1); }
 
 }  // namespace lops
 }  // namespace fmm

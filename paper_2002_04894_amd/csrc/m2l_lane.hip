@@ -41,10 +41,6 @@ __host__ __device__ constexpr int deg_of(int k) {
 }
 // index of c_{n,m} (t = 0) or s_{n,m} (t = 1) in the standard order
 __host__ __device__ constexpr int cidx(int n, int m, int t) { return n * n + (m == 0 ? 0 : 2 * m - 1 + t); }
-// floats per box of the binary32 multipoles this kernel reads: the (P+1)^2
-// coefficients in the standard order, padded to whole 16-byte loads
-__host__ __device__ constexpr int dense_stride(int p) { return ((p + 1) * (p + 1) + 3) & ~3; }
-
 // sizes of the halving exchanges: level 0 holds all NT values, each of the
 // six levels keeps the lane's half (rounded up)
 __host__ __device__ constexpr int lvl(int nt, int s) {
@@ -237,7 +233,7 @@ k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__
            double* __restrict__ Lx, int64_t ntarget, const int32_t* __restrict__ order, int* __restrict__ queue) {
   constexpr int NT = (P + 1) * (P + 1);
   constexpr int S = tl::stride(P);
-  constexpr int SD = dense_stride(P);
+  constexpr int SD = lops::dense_stride(P);
   constexpr int NF = lvl(NT, 6);  // values a lane holds after the exchanges
   constexpr bool FR = LaneCfg<P>::kFresh;
   constexpr int GJ = 64 * lops::groups(lops::n_j(P));  // table: J, J^T, z core
@@ -364,11 +360,11 @@ k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__
 // The binary32 multipoles of levels 1..L for this kernel, from the binary64
 // ones (tile layout, S per box): standard order, scaled by r^-n (r the box
 // radius, 1 for a box of zero extent; the same products as for the tile
-// kernel's copy), dense_stride(P) floats per box with a zero tail.
+// kernel's copy), lops::dense_stride(P) floats per box with a zero tail.
 template <int P>
 __global__ void k_scale_lane(LevelView lv, int S, const int* __restrict__ pos, const double* __restrict__ Mx,
                              float* __restrict__ Mf, int64_t nbox_total) {
-  constexpr int NT = (P + 1) * (P + 1), SD = dense_stride(P);
+  constexpr int NT = (P + 1) * (P + 1), SD = lops::dense_stride(P);
   const int64_t gid = 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (gid >= nbox_total) return;
   int l = 1;
@@ -395,7 +391,7 @@ template <int P>
 void launch_one_lane(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   const int64_t ntarget = t.nbox_total - 1;
   if (ntarget <= 0) return;
-  float* Mf = (float*)dalloc((size_t)t.nbox_total * dense_stride(P) * sizeof(float), s);
+  float* Mf = (float*)dalloc((size_t)t.nbox_total * lops::dense_stride(P) * sizeof(float), s);
   k_scale_lane<P><<<(unsigned)((ntarget + 3) / 4), 256, 0, s>>>(t.view(), tb.stride, tb.pos, Mx, Mf, t.nbox_total);
   HIPCHECK(hipGetLastError());
   static const int grid_max = [] {

@@ -1,0 +1,446 @@
+// M2L in binary64 (Algorithm 3, M2L; rotational form of Section 2.1.3), four
+// lanes per weak pair, the fixed quarter turns on the matrix cores.
+//
+// The translation is the sequence of the other M2L kernels:
+//   Rz(-beta), J^T, Rz(-alpha), J, z-axis translation, J^T, Rz(alpha), J, Rz(beta),
+// with J the fixed quarter turn about x and (alpha, beta) the polar and
+// azimuthal angles of d = c_source - c_target, on radius-scaled expansions
+// (M~_n = M_n / r_s^n in, the factors (r_s/rho)^n and (r_t/rho)^j / rho, the
+// result unscaled by r_t^-n), here all in binary64.
+//
+// A wave takes 16 pairs of one target box; lane 16 k + q holds phase k of
+// pair q, i.e. the members m = k (mod 4) of every block (lane_ops.h: per
+// degree two blocks indexed by the order m, the two parity classes of J).
+// Hence:
+//   - a J block is a chain of v_mfma_f64_4x4x4f64, one per (k-step, output
+//     chunk of 4 rows): the instruction's k index runs over the four phase
+//     lanes of a pair, and its output row i lands in phase i of the same pair,
+//     so every step's result is the next step's operand in place; the
+//     operator values come from LDS (binary64 instructions take no broadcast
+//     of one block's operand, so every lane reads its value);
+//   - a z-turn multiplies the (cosine, sine) parts of (d, m), which share a
+//     lane and register, by the lane's own e^{i m theta};
+//   - the z translation of order m involves only order-m coefficients of
+//     all degrees, which share a lane: each lane runs it for its orders on the
+//     vector units (binary64 vector and matrix peaks are equal on this part);
+//   - the 16 pair results are summed across the lanes by halving exchanges
+//     (fixed order: deterministic) and the batches in binary64.
+// Padding is per 4x4 part of a block: 1.57x the algorithmic J products at
+// order 12, against 2.42x for the 16x16 tiles of m2l_mfma.hip.  Orders 16..18
+// run here too (one wave per SIMD), where the tiles stop.
+#include <type_traits>
+
+#include "fmm_internal.h"
+#include "lane_ops.h"
+#include "tile_layout.h"
+
+namespace fmm {
+namespace {
+
+template <int B, int E, class F>
+__device__ __forceinline__ void qfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    qfor<B + 1, E>(f);
+  }
+}
+
+// sizes of the halving exchanges over the 16 pairs of a wave
+__host__ __device__ constexpr int qlvl(int nt, int s) {
+  int v = nt;
+  for (int k = 0; k < s; ++k) v = (v + 1) / 2;
+  return v;
+}
+
+// degree and block of register R
+__host__ __device__ constexpr int qdeg(int R) {
+  int d = 0;
+  while (lops::qbase(d + 1, 0) <= R) ++d;
+  return d;
+}
+
+__device__ __forceinline__ double mfma64(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+// One block (d, x) of a J application: NR = qreg(d) k-steps times NR output
+// chunks; tl = the lane's slot in a 16-value operand (4 k + i)
+template <int D, int X>
+struct QBlk {
+  static constexpr int NR = lops::qreg(D);
+  static constexpr int R0 = lops::qbase(D, X);
+  static constexpr int U0 = lops::qj_offset(D, X);
+  double acc[NR];
+  __device__ __forceinline__ QBlk() {
+    qfor<0, NR>([&](auto c) __attribute__((always_inline)) { acc[c] = 0.0; });
+  }
+  template <int G>
+  __device__ __forceinline__ void step(const double* X_, const double* tab, int tl) {
+    if constexpr (G < NR) {
+      const double xg = X_[R0 + G];
+      qfor<0, NR>([&](auto c) __attribute__((always_inline)) {
+        constexpr int u = U0 + G * NR + decltype(c)::value;
+        acc[c] = mfma64(tab[16 * u + tl], xg, acc[c]);
+      });
+    }
+  }
+  __device__ __forceinline__ void store(double* X_) {
+    qfor<0, NR>([&](auto c) __attribute__((always_inline)) { X_[R0 + decltype(c)::value] = acc[c]; });
+  }
+};
+
+// X <- J X (or J^T X, with that table): degree d beside degree P - d, both
+// blocks each, in lock-step over the k-steps (independent chains in flight)
+template <int P>
+__device__ __forceinline__ void qjapply(double* X, const double* tab, int tl) {
+  qfor<0, P / 2 + 1>([&](auto dI) __attribute__((always_inline)) {
+    constexpr int d = decltype(dI)::value, d2 = P - d;
+    QBlk<d, 0> a0;
+    QBlk<d, 1> a1;
+    if constexpr (d2 > d) {
+      QBlk<d2, 0> b0;
+      QBlk<d2, 1> b1;
+      qfor<0, lops::qreg(d2)>([&](auto g) __attribute__((always_inline)) {
+        constexpr int G = decltype(g)::value;
+        a0.template step<G>(X, tab, tl);
+        a1.template step<G>(X, tab, tl);
+        b0.template step<G>(X, tab, tl);
+        b1.template step<G>(X, tab, tl);
+      });
+      b0.store(X);
+      b1.store(X);
+    } else {
+      qfor<0, lops::qreg(d)>([&](auto g) __attribute__((always_inline)) {
+        constexpr int G = decltype(g)::value;
+        a0.template step<G>(X, tab, tl);
+        a1.template step<G>(X, tab, tl);
+      });
+    }
+    a0.store(X);
+    a1.store(X);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
+// X <- Rz(sign * theta) X with (c1, s1) = (cos theta, sin theta): the lane's
+// members m = 4 g + k turn by e^{i m theta}; with block 0 holding c_m for
+// even m and s_m for odd m, the turn of (b0, b1) is (C b0 - S' b1, S' b0 +
+// C b1) with S' = S for even m and -S for odd m
+template <int P>
+__device__ __forceinline__ void qrotz(double* X, double c1, double s1, double sign, int k) {
+  constexpr int NG = P / 4 + 1;
+  // e^{i k theta} and e^{i 4 theta}
+  const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * s1 * c1;
+  const double c3 = c2 * c1 - s2 * s1, s3 = s2 * c1 + c2 * s1;
+  const double c4 = c2 * c2 - s2 * s2, s4 = 2.0 * s2 * c2;
+  double cc = k == 0 ? 1.0 : k == 1 ? c1 : k == 2 ? c2 : c3;
+  double ss = k == 0 ? 0.0 : k == 1 ? s1 : k == 2 ? s2 : s3;
+  const double par = (k & 1) ? -sign : sign;
+  double C[NG], S[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    C[g] = cc;
+    S[g] = par * ss;
+    const double nc = cc * c4 - ss * s4, ns = ss * c4 + cc * s4;
+    cc = nc;
+    ss = ns;
+  }
+  qfor<0, P + 1>([&](auto dI) __attribute__((always_inline)) {
+    constexpr int d = decltype(dI)::value;
+    qfor<0, lops::qreg(d)>([&](auto g) __attribute__((always_inline)) {
+      constexpr int G = decltype(g)::value;
+      constexpr int r0 = lops::qbase(d, 0) + G, r1 = lops::qbase(d, 1) + G;
+      const double b0 = X[r0], b1 = X[r1];
+      X[r0] = C[G] * b0 - S[G] * b1;
+      X[r1] = S[G] * b0 + C[G] * b1;
+    });
+  });
+}
+
+// the z-axis translation: the lane's orders m = 4 g + k, both blocks, with
+// the core A[m][d][n] of its own order (Az, orders above P zero)
+template <int P>
+__device__ __forceinline__ void qztrans(double* X, const double* __restrict__ Az, int k, double in_base,
+                                        double out_base, double out_mult) {
+  constexpr int P1 = P + 1;
+  {
+    double w = 1.0;
+    qfor<0, P + 1>([&](auto dI) __attribute__((always_inline)) {
+      constexpr int d = decltype(dI)::value;
+      qfor<0, 2 * lops::qreg(d)>([&](auto r) __attribute__((always_inline)) {
+        X[lops::qbase(d, 0) + decltype(r)::value] *= w;
+      });
+      w *= in_base;
+    });
+  }
+  qfor<0, P / 4 + 1>([&](auto gI) __attribute__((always_inline)) {
+    constexpr int G = decltype(gI)::value;
+    constexpr int N0 = 4 * G;  // lowest degree holding register G
+    // the lane's order, orders above P reading the zero slot P + 1
+    const double* Am = Az + (4 * G + k <= P ? 4 * G + k : P + 1) * P1 * P1;
+    double y0[P1 - N0], y1[P1 - N0];
+    qfor<0, P1 - N0>([&](auto r) __attribute__((always_inline)) { y0[r] = y1[r] = 0.0; });
+    // input degree by input degree: only one column of the core is loaded
+    // at a time (all of them at once would not fit the registers)
+    qfor<N0, P1>([&](auto nI) __attribute__((always_inline)) {
+      constexpr int n = decltype(nI)::value;
+      const double x0 = X[lops::qbase(n, 0) + G], x1 = X[lops::qbase(n, 1) + G];
+      qfor<N0, P1>([&](auto dI) __attribute__((always_inline)) {
+        constexpr int d = decltype(dI)::value;
+        const double a = Am[d * P1 + n];
+        y0[d - N0] += a * x0;
+        y1[d - N0] += a * x1;
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    qfor<N0, P1>([&](auto dI) __attribute__((always_inline)) {
+      constexpr int d = decltype(dI)::value;
+      X[lops::qbase(d, 0) + G] = y0[d - N0];
+      X[lops::qbase(d, 1) + G] = y1[d - N0];
+    });
+  });
+  {
+    double w = out_mult;
+    qfor<0, P + 1>([&](auto dI) __attribute__((always_inline)) {
+      constexpr int d = decltype(dI)::value;
+      qfor<0, 2 * lops::qreg(d)>([&](auto r) __attribute__((always_inline)) {
+        X[lops::qbase(d, 0) + decltype(r)::value] *= w;
+      });
+      w *= out_base;
+    });
+  }
+}
+
+__device__ __forceinline__ int qlevel_of(const LevelView& lv, int64_t gid) {
+  int l = 0;
+  while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
+  return l;
+}
+
+// Waves per SIMD: 2 up to order 13, 1 from 16 on.  One block per CU (512 threads
+// for two waves per SIMD, 256 for one), so that the tables (J, J^T and the z
+// core: 55 KB at order 12, 158 KB at 18) are staged into LDS once per CU.
+template <int P>
+struct QuadCfg {
+  static constexpr int kWaves = P <= 13 ? 2 : 1;
+  static constexpr int kThreads = 256 * kWaves;
+  static constexpr int kJ = 16 * lops::qj_count(P);  // doubles per J table
+  static constexpr int kLds = lops::qtable_doubles(P);
+  static_assert(kLds * 8 <= 160 * 1024, "the tables must fit in LDS");
+};
+
+template <int P>
+__global__ __launch_bounds__(QuadCfg<P>::kThreads) __attribute__((amdgpu_waves_per_eu(QuadCfg<P>::kWaves, QuadCfg<P>::kWaves))) void
+k_m2l_quad(LevelView lv, const double* __restrict__ qtab, const int* __restrict__ pos, int S,
+           const double* __restrict__ Mq, double* __restrict__ Lx, int64_t ntarget, const int32_t* __restrict__ order,
+           int* __restrict__ queue) {
+  constexpr int NQ = lops::nq(P);
+  constexpr int NJ = QuadCfg<P>::kJ;
+  constexpr int NF = qlvl(NQ, 4);  // values a lane holds after the exchanges
+  constexpr int NL = QuadCfg<P>::kLds;
+  __shared__ double tabs[NL];
+  for (int i = threadIdx.x; i < NL; i += blockDim.x) tabs[i] = qtab[i];
+  __syncthreads();
+  const double* Az = tabs + 2 * NJ;
+  const int lane = threadIdx.x & 63;
+  const int k = lane >> 4, q = lane & 15;
+  const int tl = 4 * k + (lane & 3);  // this lane's value in a 4x4 operand part
+  for (;;) {
+    int kq = 0;
+    if (lane == 0) kq = atomicAdd(queue, 1);
+    kq = __builtin_amdgcn_readfirstlane(kq);
+    if (kq >= ntarget) break;
+    const int64_t gid = lv.gofs[1] + order[kq];
+    const int l = qlevel_of(lv, gid);
+    const int64_t bi = gid - lv.gofs[l];
+    const double* geo = lv.geom[l];
+    const double cix = geo[bi * 10 + 6], ciy = geo[bi * 10 + 7], ciz = geo[bi * 10 + 8];
+    const double rt = geo[bi * 10 + 9] > 0.0 ? geo[bi * 10 + 9] : 1.0;
+    const int64_t e0 = lv.w_off[l][bi], e1 = lv.w_off[l][bi + 1];
+    const int32_t* widx = lv.w_idx[l];
+    const double* Mlev = Mq + (size_t)lv.gofs[l] * NQ * 4;
+    double acc[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) acc[i] = 0.0;
+
+    for (int64_t eb = e0; eb < e1; eb += 16) {
+      const int64_t e = eb + q;
+      const bool valid = e < e1;
+      const int64_t j = widx[valid ? e : e0];
+      const double dx = geo[j * 10 + 6] - cix, dy = geo[j * 10 + 7] - ciy, dz = geo[j * 10 + 8] - ciz;
+      const double rs = geo[j * 10 + 9] > 0.0 ? geo[j * 10 + 9] : 1.0;
+      const double rxy2 = dx * dx + dy * dy;
+      const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
+      const double irho = 1.0 / rho;
+      const double ca = dz * irho, sa = rxy * irho;
+      const double cb = rxy > 0.0 ? dx / rxy : 1.0, sb = rxy > 0.0 ? dy / rxy : 0.0;
+      // a pair past the end of the list translates the first source with zero factors
+      const double in_base = valid ? rs * irho : 0.0;
+      const double out_base = valid ? rt * irho : 0.0;
+      const double out_mult = valid ? irho : 0.0;
+
+      double X[NQ];
+      const double* src = Mlev + (size_t)j * NQ * 4 + k;
+#pragma unroll
+      for (int r = 0; r < NQ; ++r) X[r] = src[4 * r];
+
+#define FMM_QSTEP(x) \
+  x;                 \
+  __builtin_amdgcn_sched_barrier(0)
+      FMM_QSTEP(qrotz<P>(X, cb, sb, -1.0, k));
+      FMM_QSTEP(qjapply<P>(X, tabs + NJ, tl));
+      FMM_QSTEP(qrotz<P>(X, ca, sa, -1.0, k));
+      FMM_QSTEP(qjapply<P>(X, tabs, tl));
+      FMM_QSTEP(qztrans<P>(X, Az, k, in_base, out_base, out_mult));
+      FMM_QSTEP(qjapply<P>(X, tabs + NJ, tl));
+      FMM_QSTEP(qrotz<P>(X, ca, sa, 1.0, k));
+      FMM_QSTEP(qjapply<P>(X, tabs, tl));
+      FMM_QSTEP(qrotz<P>(X, cb, sb, 1.0, k));
+#undef FMM_QSTEP
+
+      // sum over the 16 pairs (lane bits 0..3): four halving exchanges; at
+      // the exchange with lane distance dist the lanes with that bit clear
+      // keep the lower half
+#define FMM_QHALVE(SRC, N_SRC, DST, N_DST, DIST)                         \
+  double DST[N_DST];                                                    \
+  {                                                                     \
+    const bool up = (lane & (DIST)) != 0;                               \
+    _Pragma("unroll") for (int i = 0; i < (N_DST); ++i) {               \
+      const int ih = (N_DST) + i < (N_SRC) ? (N_DST) + i : (N_SRC) - 1; \
+      const double lo = SRC[i];                                         \
+      const double hi = (N_DST) + i < (N_SRC) ? SRC[ih] : 0.0;          \
+      const double send = up ? lo : hi;                                 \
+      const double keep = up ? hi : lo;                                 \
+      DST[i] = keep + __shfl_xor(send, (DIST));                         \
+      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);              \
+    }                                                                   \
+  }
+      FMM_QHALVE(X, NQ, h1, qlvl(NQ, 1), 8)
+      FMM_QHALVE(h1, qlvl(NQ, 1), h2, qlvl(NQ, 2), 4)
+      FMM_QHALVE(h2, qlvl(NQ, 2), h3, qlvl(NQ, 3), 2)
+      FMM_QHALVE(h3, qlvl(NQ, 3), h4, qlvl(NQ, 4), 1)
+#undef FMM_QHALVE
+#pragma unroll
+      for (int i = 0; i < NF; ++i) acc[i] += h4[i];
+    }
+    // lane's values: registers base + i of phase k, where each exchange
+    // added the kept half's offset; entries past a half's end are padding
+    int base = 0, len = NQ;
+#pragma unroll
+    for (int sidx = 1; sidx <= 4; ++sidx) {
+      const int half = qlvl(NQ, sidx);
+      const int dist = 16 >> sidx;
+      if (lane & dist) {
+        base += half;
+        len = len - half > 0 ? len - half : 0;
+      } else {
+        len = len < half ? len : half;
+      }
+    }
+    double* dst = Lx + (size_t)gid * S;
+    const double irt = 1.0 / rt;
+    qfor<0, NF>([&](auto iI) __attribute__((always_inline)) {
+      constexpr int i = decltype(iI)::value;
+      if (i < len) {
+        const int R = base + i;
+        const int d = qdeg(R);
+        const int x = R - lops::qbase(d, 0) >= lops::qreg(d) ? 1 : 0;
+        const int g = R - lops::qbase(d, x);
+        const int mi = lops::qmember(d, x, 4 * g + k);
+        if (mi >= 0) {
+          double v = acc[i];
+          for (int t = 0; t < d; ++t) v *= irt;
+          dst[pos[d * d + mi]] = v;
+        }
+      }
+    });
+  }
+}
+
+// The multipoles of levels 1..L in the quad layout, scaled by r^-n (r the box
+// radius, 1 for a box of zero extent): per box NQ registers x 4 phases.
+template <int P>
+__global__ void k_quad_copy(LevelView lv, int S, const int* __restrict__ pos, const double* __restrict__ Mx,
+                            double* __restrict__ Mq, int64_t nbox_total) {
+  constexpr int NQ = lops::nq(P);
+  const int64_t gid = 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gid >= nbox_total) return;
+  int l = 1;
+  while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
+  const double r = lv.geom[l][(gid - lv.gofs[l]) * 10 + 9];
+  const double is = r > 0.0 ? 1.0 / r : 1.0;
+  for (int t = threadIdx.x & 63; t < 4 * NQ; t += 64) {
+    const int R = t >> 2, k = t & 3;
+    const int d = qdeg(R);
+    const int x = R - lops::qbase(d, 0) >= lops::qreg(d) ? 1 : 0;
+    const int g = R - lops::qbase(d, x);
+    const int mi = lops::qmember(d, x, 4 * g + k);
+    double v = 0.0;
+    if (mi >= 0) {
+      v = Mx[(size_t)gid * S + pos[d * d + mi]];
+      for (int u = 0; u < d; ++u) v *= is;
+    }
+    Mq[(size_t)gid * NQ * 4 + t] = v;
+  }
+}
+
+__global__ void k_zero_queue_q(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
+}
+
+template <int P>
+void launch_one_quad(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
+  const int64_t ntarget = t.nbox_total - 1;
+  if (ntarget <= 0) return;
+  constexpr int NQ = lops::nq(P);
+  double* Mq = (double*)dalloc((size_t)t.nbox_total * NQ * 4 * sizeof(double), s);
+  k_quad_copy<P><<<(unsigned)((ntarget + 3) / 4), 256, 0, s>>>(t.view(), tb.stride, tb.pos, Mx, Mq, t.nbox_total);
+  HIPCHECK(hipGetLastError());
+  static const int grid_max = [] {
+    int dev = 0, ncu = 0, per = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_m2l_quad<P>, QuadCfg<P>::kThreads, 0));
+    return ncu * (per > 0 ? per : 1);
+  }();
+  const int64_t need = (ntarget + QuadCfg<P>::kThreads / 64 - 1) / (QuadCfg<P>::kThreads / 64);
+  const unsigned grid = (unsigned)(need < grid_max ? need : grid_max);
+  int* queue = (int*)dalloc(sizeof(int), s);
+  k_zero_queue_q<<<1, 64, 0, s>>>(queue);
+  HIPCHECK(hipGetLastError());
+  k_m2l_quad<P><<<grid, QuadCfg<P>::kThreads, 0, s>>>(t.view(), tb.quad, tb.pos, tb.stride, Mq, Lx, ntarget, t.m2l_order, queue);
+  HIPCHECK(hipGetLastError());
+  dfree(queue, s);
+  dfree(Mq, s);
+}
+
+}  // namespace
+
+// binary64 M2L with this kernel: orders up to 13 and 16..18; false for the
+// others (14 and 15: the 16x16 tile kernel is faster, the two-wave quad
+// kernel spills; above 18 its tables no longer fit in LDS)
+bool launch_m2l_quad64(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
+  switch (tb.p) {
+    case 0: launch_one_quad<0>(t, tb, Mx, Lx, s); break;
+    case 1: launch_one_quad<1>(t, tb, Mx, Lx, s); break;
+    case 2: launch_one_quad<2>(t, tb, Mx, Lx, s); break;
+    case 3: launch_one_quad<3>(t, tb, Mx, Lx, s); break;
+    case 4: launch_one_quad<4>(t, tb, Mx, Lx, s); break;
+    case 5: launch_one_quad<5>(t, tb, Mx, Lx, s); break;
+    case 6: launch_one_quad<6>(t, tb, Mx, Lx, s); break;
+    case 7: launch_one_quad<7>(t, tb, Mx, Lx, s); break;
+    case 8: launch_one_quad<8>(t, tb, Mx, Lx, s); break;
+    case 9: launch_one_quad<9>(t, tb, Mx, Lx, s); break;
+    case 10: launch_one_quad<10>(t, tb, Mx, Lx, s); break;
+    case 11: launch_one_quad<11>(t, tb, Mx, Lx, s); break;
+    case 12: launch_one_quad<12>(t, tb, Mx, Lx, s); break;
+    case 13: launch_one_quad<13>(t, tb, Mx, Lx, s); break;
+    case 16: launch_one_quad<16>(t, tb, Mx, Lx, s); break;
+    case 17: launch_one_quad<17>(t, tb, Mx, Lx, s); break;
+    case 18: launch_one_quad<18>(t, tb, Mx, Lx, s); break;
+    default: return false;
+  }
+  return true;
+}
+
+}  // namespace fmm

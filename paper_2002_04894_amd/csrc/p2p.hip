@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "fmm_internal.h"
+#include "lane_ops.h"
 #include "tile_layout.h"
 
 namespace fmm {
@@ -590,11 +591,15 @@ size_t eval_scratch_bytes(const Tree& t, int p, int prec) {
   auto one = [&](int64_t npts, int64_t npart) {
     const size_t qt = (size_t)t.n * 8;
     const size_t far = t.L >= 1 ? 4 * (size_t)std::max<int64_t>(1, npts) * 8 : 0;
+    // the M2L kernel's own copy of the multipoles, per box: binary32 dense
+    // (per-lane kernel, orders up to 14) or tiled (order 15), else binary64
+    // in the quad layout (orders up to 13 and 16..18)
+    size_t copy = 0;
+    if (prec != FMM_PREC_F64 && p <= 14) copy = (size_t)lops::dense_stride(p) * 4;
+    else if (prec != FMM_PREC_F64 && p <= tl::kMaxP) copy = stride * 4;
+    else if (p <= 13 || (p >= 16 && p <= 18)) copy = (size_t)lops::nq(p) * 4 * 8;
     size_t expn = 0;
-    if (t.L >= 1) {
-      expn = 2 * nbox * stride * 8 + 256;                        // multipoles, locals, M2L queue
-      if (prec != FMM_PREC_F64 && p <= tl::kMaxP) expn += nbox * stride * 4;  // binary32 multipoles
-    }
+    if (t.L >= 1) expn = 2 * nbox * stride * 8 + 256 + nbox * copy;  // multipoles, locals, M2L queue, copy
     const size_t part = (size_t)std::max<int64_t>(0, npart) * 32;
     return qt + far + std::max(expn, part);
   };
