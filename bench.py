@@ -33,6 +33,12 @@ from paper_2002_04894_amd import fmm, workloads  # noqa: E402
 FP64_PEAK_TFLOPS = 78.6        # MI355X binary64 vector (and matrix) peak
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X binary32 matrix peak (dense)
 LANE_M2L_MAX_P = 14            # mixed precision: the per-lane M2L kernel up to this order, 16x16 tiles above
+
+
+def quad_m2l(p: int) -> bool:
+    """binary64 M2L runs four lanes per pair at these orders (16x16 tiles at
+    14 and 15, the vector kernel above 18)"""
+    return p <= 13 or 16 <= p <= 18
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one M2L launch, per kernel and workload: from two rocprofv3
@@ -44,11 +50,16 @@ HBM_PEAK_GBS = 8000.0
 COPY_FETCH_SCALE = 1048576.0 / 524308.4375
 COPY_WRITE_SCALE = 1.0
 M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
-    # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12, mixed precision)
+    # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12): mixed precision and binary64
     ("k_m2l_lane<12>", 1 << 27, 0.6): {
-        "sources_sha256": "a2295f4a9a3f178d7bda493cb329aff43a8237a6b32dbbd8f7377b103189b8a6",
-        "fetch_kib": 4279972417.8125,
-        "write_kib": 635745128.6875,
+        "sources_sha256": "8c08ca3e23531b4f1b68c0a5e8d162469b7f9b8d950ef846f9ee7637a11ec5f1",
+        "fetch_kib": 4276971058.125,
+        "write_kib": 635765815.3125,
+    },
+    ("k_m2l_quad<12>", 1 << 27, 0.6): {
+        "sources_sha256": "ab6b2503ac03601fcc581788abd34db077d20876357df5a7230159c354e491b0",
+        "fetch_kib": 10546731641.875,
+        "write_kib": 17000206.6875,
     },
 }
 
@@ -56,8 +67,9 @@ M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", 
 def m2l_sources_sha256(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in (("m2l_lane.hip", "lane_ops.h") if kernel.startswith("k_m2l_lane") else ("m2l_mfma.hip",)) + (
-            "tile_layout.h",):
+    files = {"k_m2l_lane": ("m2l_lane.hip", "lane_ops.h"), "k_m2l_quad": ("m2l_quad.hip", "lane_ops.h")}.get(
+        kernel.split("<")[0], ("m2l_mfma.hip",))
+    for f in files + ("tile_layout.h",):
         with open(os.path.join(ROOT, "paper_2002_04894_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -239,6 +251,8 @@ def timed_leg(X, Y, Z, Q, L, theta, p, prec, outs, steps, warmup, stream, torch)
     mixed = prec == fmm.FMM_PREC_MIXED and p <= 15
     if mixed and p <= LANE_M2L_MAX_P:
         kernel, bound, peak = f"k_m2l_lane<{p}>", "mfma", FP32_MFMA_PEAK_TFLOPS
+    elif not mixed and quad_m2l(p):
+        kernel, bound, peak = f"k_m2l_quad<{p}>", "mfma", FP64_PEAK_TFLOPS
     elif p <= 15:
         kernel = f"k_m2l_mfma<{p}, {'float' if mixed else 'double'}>"
         bound, peak = "mfma", FP32_MFMA_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
