@@ -4,8 +4,9 @@
 // connected to the parent of i, in ascending order; a distinct candidate j
 // with centre distance d > 0 is weakly connected iff R + theta*r <= theta*d
 // (R, r the larger and smaller radius), otherwise strongly connected.  The
-// lists are CSR by target box: a count pass, a scan, and a fill pass (the
-// same loop writing indices), so each row comes out in ascending order.
+// lists are CSR by target box: a count pass (which keeps every outcome as a
+// bit), a scan, and a fill pass over the same candidates in the same order,
+// so each row comes out in ascending order.
 #include <algorithm>
 
 #include "fmm_internal.h"
@@ -33,12 +34,31 @@ __device__ __forceinline__ bool is_weak(const double* gi, double cjx, double cjy
 // geometry loads are issued before any of them is tested.
 constexpr int kListGroups = 4;
 
-template <bool FILL>
-__global__ __launch_bounds__(256) void k_lists(int64_t nbox, const double* __restrict__ geom,
-                                               const int64_t* __restrict__ ps_off, const int32_t* __restrict__ ps_idx,
-                                               double theta, int32_t* __restrict__ ns, int32_t* __restrict__ nw,
-                                               const int64_t* __restrict__ s_off, int32_t* __restrict__ s_idx,
-                                               const int64_t* __restrict__ w_off, int32_t* __restrict__ w_idx) {
+// Candidate centre and radius as one 32-byte record per box (one load per
+// candidate instead of four at the 80-byte stride of the box geometry).
+__global__ void k_centre_radius(int64_t nbox, const double* __restrict__ geom, double4* __restrict__ cr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nbox) cr[i] = make_double4(geom[i * 10 + 6], geom[i * 10 + 7], geom[i * 10 + 8], geom[i * 10 + 9]);
+}
+
+// 64-bit mask words per child of each parent: ceil(8 |strong(parent)| / 64)
+__global__ void k_mask_words(int64_t npar, const int64_t* __restrict__ ps_off, int32_t* __restrict__ words) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npar) words[p] = (int32_t)((ps_off[p + 1] - ps_off[p] + 7) / 8);
+}
+
+// Count pass: the theta test of every candidate of box i; the weak outcome
+// of each group of 64 candidates is kept as one mask word (box i's words
+// start at 8 wofs[parent] + child * words[parent]), and the counts of the
+// row are written.
+__global__ __launch_bounds__(256) void k_lists_count(int64_t nbox, const double* __restrict__ geom,
+                                                     const double4* __restrict__ cr,
+                                                     const int64_t* __restrict__ ps_off,
+                                                     const int32_t* __restrict__ ps_idx, double theta,
+                                                     const int64_t* __restrict__ wofs,
+                                                     const int32_t* __restrict__ words,
+                                                     uint64_t* __restrict__ mask, int32_t* __restrict__ ns,
+                                                     int32_t* __restrict__ nw) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= nbox) return;
@@ -46,12 +66,7 @@ __global__ __launch_bounds__(256) void k_lists(int64_t nbox, const double* __res
   const double* gi = geom + i * 10;
   const int64_t e0 = ps_off[par];
   const int64_t ncand = 8 * (ps_off[par + 1] - e0);
-  const uint64_t below = (1ull << lane) - 1ull;
-  int64_t so = 0, wo = 0;
-  if (FILL) {
-    so = s_off[i];
-    wo = w_off[i];
-  }
+  uint64_t* mrow = mask + 8 * wofs[par] + (i & 7) * (int64_t)words[par];
   int64_t cs = 0, cw = 0;
   for (int64_t k0 = 0; k0 < ncand; k0 += 64 * kListGroups) {
     int64_t j[kListGroups];
@@ -62,27 +77,64 @@ __global__ __launch_bounds__(256) void k_lists(int64_t nbox, const double* __res
       valid[u] = k < ncand;
       j[u] = valid[u] ? 8 * (int64_t)ps_idx[e0 + (k >> 3)] + (k & 7) : i;
     }
-    double c[kListGroups][4];
+    double4 c[kListGroups];
 #pragma unroll
-    for (int u = 0; u < kListGroups; ++u)
-#pragma unroll
-      for (int a = 0; a < 4; ++a) c[u][a] = geom[j[u] * 10 + 6 + a];
+    for (int u = 0; u < kListGroups; ++u) c[u] = cr[j[u]];
 #pragma unroll
     for (int u = 0; u < kListGroups; ++u) {
-      const bool weak = valid[u] && (j[u] != i) && is_weak(gi, c[u][0], c[u][1], c[u][2], c[u][3], theta);
+      const bool weak = valid[u] && (j[u] != i) && is_weak(gi, c[u].x, c[u].y, c[u].z, c[u].w, theta);
       const bool strong = valid[u] && !weak;
       const uint64_t mw = __ballot(weak), ms = __ballot(strong);
-      if (FILL) {
-        if (weak) w_idx[wo + cw + __popcll(mw & below)] = (int32_t)j[u];
-        if (strong) s_idx[so + cs + __popcll(ms & below)] = (int32_t)j[u];
-      }
+      const int64_t g = k0 / 64 + u;
+      if (lane == 0 && 64 * g < ncand) mrow[g] = mw;
       cw += __popcll(mw);
       cs += __popcll(ms);
     }
   }
-  if (!FILL && lane == 0) {
+  if (lane == 0) {
     ns[i] = (int32_t)cs;
     nw[i] = (int32_t)cw;
+  }
+}
+
+// Fill pass: the candidates again, in the same order, sorted into the rows
+// by the count pass's mask words (no geometry, no test).
+__global__ __launch_bounds__(256) void k_lists_fill(int64_t nbox, const int64_t* __restrict__ ps_off,
+                                                    const int32_t* __restrict__ ps_idx,
+                                                    const int64_t* __restrict__ wofs,
+                                                    const int32_t* __restrict__ words,
+                                                    const uint64_t* __restrict__ mask,
+                                                    const int64_t* __restrict__ s_off, int32_t* __restrict__ s_idx,
+                                                    const int64_t* __restrict__ w_off, int32_t* __restrict__ w_idx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nbox) return;
+  const int64_t par = i >> 3;
+  const int64_t e0 = ps_off[par];
+  const int64_t ncand = 8 * (ps_off[par + 1] - e0);
+  const uint64_t* mrow = mask + 8 * wofs[par] + (i & 7) * (int64_t)words[par];
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t so = s_off[i], wo = w_off[i];
+  int64_t cs = 0, cw = 0;
+  for (int64_t k0 = 0; k0 < ncand; k0 += 64 * kListGroups) {
+    int32_t j[kListGroups];
+#pragma unroll
+    for (int u = 0; u < kListGroups; ++u) {
+      const int64_t k = k0 + 64 * u + lane;
+      j[u] = k < ncand ? 8 * ps_idx[e0 + (k >> 3)] + (int32_t)(k & 7) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kListGroups; ++u) {
+      const int64_t g = k0 / 64 + u;
+      if (64 * g >= ncand) break;
+      const int64_t left = ncand - 64 * g;
+      const uint64_t vm = left >= 64 ? ~0ull : ((1ull << left) - 1ull);
+      const uint64_t mw = mrow[g], ms = vm & ~mw;
+      if ((mw >> lane) & 1ull) w_idx[wo + cw + __popcll(mw & below)] = j[u];
+      if ((ms >> lane) & 1ull) s_idx[so + cs + __popcll(ms & below)] = j[u];
+      cw += __popcll(mw);
+      cs += __popcll(ms);
+    }
   }
 }
 
@@ -237,11 +289,23 @@ void lists_build(Tree& t, hipStream_t s) {
     Level& P = t.lev[l - 1];
     Level& V = t.lev[l];
     const int64_t nb = V.nbox;
+    const int64_t npar = P.nbox;
     int32_t* ns = (int32_t*)dalloc(nb * sizeof(int32_t), s);
     int32_t* nw = (int32_t*)dalloc(nb * sizeof(int32_t), s);
+    double4* cr = (double4*)dalloc(nb * sizeof(double4), s);
+    int32_t* words = (int32_t*)dalloc(npar * sizeof(int32_t), s);
+    int64_t* wofs = (int64_t*)dalloc((npar + 1) * sizeof(int64_t), s);
+    k_centre_radius<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(nb, V.geom, cr);
+    HIPCHECK(hipGetLastError());
+    k_mask_words<<<(unsigned)((npar + 255) / 256), 256, 0, s>>>(npar, P.s_off, words);
+    HIPCHECK(hipGetLastError());
+    scan_counts(words, wofs, npar, 0, s);
+    // mask words in all: 8 sum_p ceil(S_p / 8) <= (the parents' strong
+    // entries) + 8 npar, known on the host without a read-back
+    const int64_t nwords = P.s_nnz + 8 * npar;
+    uint64_t* mask = (uint64_t*)dalloc(std::max<int64_t>(1, nwords) * sizeof(uint64_t), s);
     const unsigned grid = (unsigned)((nb + 3) / 4);
-    k_lists<false><<<grid, 256, 0, s>>>(nb, V.geom, P.s_off, P.s_idx, t.theta, ns, nw, nullptr, nullptr, nullptr,
-                                        nullptr);
+    k_lists_count<<<grid, 256, 0, s>>>(nb, V.geom, cr, P.s_off, P.s_idx, t.theta, wofs, words, mask, ns, nw);
     HIPCHECK(hipGetLastError());
     V.s_off = (int64_t*)dalloc((nb + 1) * sizeof(int64_t), s);
     V.w_off = (int64_t*)dalloc((nb + 1) * sizeof(int64_t), s);
@@ -255,9 +319,13 @@ void lists_build(Tree& t, hipStream_t s) {
     m2l += V.w_nnz;
     V.s_idx = (int32_t*)dalloc(std::max<int64_t>(1, V.s_nnz) * sizeof(int32_t), s);
     V.w_idx = (int32_t*)dalloc(std::max<int64_t>(1, V.w_nnz) * sizeof(int32_t), s);
-    k_lists<true><<<grid, 256, 0, s>>>(nb, V.geom, P.s_off, P.s_idx, t.theta, nullptr, nullptr, V.s_off, V.s_idx,
-                                       V.w_off, V.w_idx);
+    k_lists_fill<<<grid, 256, 0, s>>>(nb, P.s_off, P.s_idx, wofs, words, mask, V.s_off, V.s_idx, V.w_off,
+                                      V.w_idx);
     HIPCHECK(hipGetLastError());
+    dfree(mask, s);
+    dfree(wofs, s);
+    dfree(words, s);
+    dfree(cr, s);
     dfree(ns, s);
     dfree(nw, s);
   }
