@@ -212,6 +212,42 @@ __device__ __forceinline__ void ztrans_mf(float* X, const float* tab, int lane, 
   }
 }
 
+// One halving exchange of the sum over the lanes: dst[i] = src[i] of this
+// lane and of its partner at lane distance D (lanes with bit D clear) or
+// src[NS/2 + i] of both (bit set); the upper half of an odd count is padded
+// with zero.  Distances 32 and 16 are permlane swaps (the swap of (lower,
+// upper) leaves each lane the two terms of its own sum), 8, 2 and 1 a DPP
+// read of the partner, 4 two DPP shifts.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int NS, int D>
+__device__ __forceinline__ void halve(const float* src, float* dst, int lane) {
+  constexpr int ND = (NS + 1) / 2;
+  const bool up = (lane & D) != 0;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    const float lo = src[i];
+    const float hi = ND + i < NS ? src[ND + i] : 0.f;
+    if constexpr (D == 32 || D == 16) {
+      const auto r = D == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                             : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+      dst[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else if constexpr (D == 4) {
+      // row_shl:4 reads lane + 4, row_shr:4 lane - 4 (within rows of 16)
+      const float t0 = lo + dpp<0x104>(lo), t1 = hi + dpp<0x114>(hi);
+      dst[i] = up ? t1 : t0;
+    } else {
+      // the partner lane^D: row_ror:8, quad_perm [2,3,0,1], [1,0,3,2]
+      constexpr int C = D == 8 ? 0x128 : D == 2 ? 0x4E : 0xB1;
+      const float send = up ? lo : hi, keep = up ? hi : lo;
+      dst[i] = keep + dpp<C>(send);
+    }
+    if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);  // a few in flight: bounded registers
+  }
+}
+
 __device__ __forceinline__ int level_of3(const LevelView& lv, int64_t gid) {
   int l = 0;
   while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
@@ -304,28 +340,13 @@ k_m2l_lane(LevelView lv, const float* __restrict__ ltab, const int* __restrict__
 
       // sum over the 64 lanes: six halving exchanges; at the exchange with
       // lane distance d the lanes with bit d clear keep the lower half
-#define FMM_HALVE(SRC, N_SRC, DST, N_DST, DIST)                          \
-  float DST[N_DST];                                                     \
-  {                                                                     \
-    const bool up = (lane & (DIST)) != 0;                               \
-    _Pragma("unroll") for (int i = 0; i < (N_DST); ++i) {               \
-      const int ih = (N_DST) + i < (N_SRC) ? (N_DST) + i : (N_SRC) - 1; \
-      const float lo = SRC[i];                                          \
-      const float hi = (N_DST) + i < (N_SRC) ? SRC[ih] : 0.f;           \
-      const float send = up ? lo : hi;                                  \
-      const float keep = up ? hi : lo;                                  \
-      DST[i] = keep + __shfl_xor(send, (DIST));                         \
-      /* a few exchanges in flight at a time: bounded registers */      \
-      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);              \
-    }                                                                   \
-  }
-      FMM_HALVE(X, NT, h1, lvl(NT, 1), 32)
-      FMM_HALVE(h1, lvl(NT, 1), h2, lvl(NT, 2), 16)
-      FMM_HALVE(h2, lvl(NT, 2), h3, lvl(NT, 3), 8)
-      FMM_HALVE(h3, lvl(NT, 3), h4, lvl(NT, 4), 4)
-      FMM_HALVE(h4, lvl(NT, 4), h5, lvl(NT, 5), 2)
-      FMM_HALVE(h5, lvl(NT, 5), h6, lvl(NT, 6), 1)
-#undef FMM_HALVE
+      float h1[lvl(NT, 1)], h2[lvl(NT, 2)], h3[lvl(NT, 3)], h4[lvl(NT, 4)], h5[lvl(NT, 5)], h6[lvl(NT, 6)];
+      halve<NT, 32>(X, h1, lane);
+      halve<lvl(NT, 1), 16>(h1, h2, lane);
+      halve<lvl(NT, 2), 8>(h2, h3, lane);
+      halve<lvl(NT, 3), 4>(h3, h4, lane);
+      halve<lvl(NT, 4), 2>(h4, h5, lane);
+      halve<lvl(NT, 5), 1>(h5, h6, lane);
 #pragma unroll
       for (int i = 0; i < NF; ++i) acc[i] += (double)h6[i];
     }
