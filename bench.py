@@ -52,9 +52,9 @@ COPY_WRITE_SCALE = 1.0
 M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
     # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12): mixed precision and binary64
     ("k_m2l_lane<12>", 1 << 27, 0.6): {
-        "sources_sha256": "8c08ca3e23531b4f1b68c0a5e8d162469b7f9b8d950ef846f9ee7637a11ec5f1",
-        "fetch_kib": 4276971058.125,
-        "write_kib": 635765815.3125,
+        "sources_sha256": "ab7fb94fdcf701d71b6636f8be950a39e390edd137c367607f90ea5215d786a1",
+        "fetch_kib": 3976133030.875,
+        "write_kib": 479565723.84375,
     },
     ("k_m2l_quad<12>", 1 << 27, 0.6): {
         "sources_sha256": "ab6b2503ac03601fcc581788abd34db077d20876357df5a7230159c354e491b0",
