@@ -35,11 +35,15 @@ __global__ void k_gather(const double* __restrict__ q, const int32_t* __restrict
 }
 
 // 1/sqrt(r2) to full double precision: hardware estimate + one Newton step
-// (relative error below 5e-15); 0 for r2 == 0.
+// (relative error below 5e-15); 0 for r2 == 0.  The estimate of +0 is +inf,
+// whose low word is zero, so clearing its high word gives +0 and the Newton
+// step then keeps 0: one select of one word instead of two on the result.
 __device__ __forceinline__ double rsqrt_nr(double r2) {
-  const double y0 = __builtin_amdgcn_rsq(r2);
-  const double y1 = y0 * (1.5 - 0.5 * r2 * y0 * y0);
-  return r2 > 0.0 ? y1 : 0.0;
+  const double e = __builtin_amdgcn_rsq(r2);
+  const long long b = __double_as_longlong(e);
+  const int hi = r2 > 0.0 ? (int)(b >> 32) : 0;
+  const double y0 = __hiloint2double(hi, (int)b);
+  return y0 * (1.5 - 0.5 * r2 * y0 * y0);
 }
 
 // Work items (segments, in leaf order) are mapped to blocks so that
