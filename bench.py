@@ -52,7 +52,7 @@ COPY_WRITE_SCALE = 1.0
 M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
     # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12): mixed precision and binary64
     ("k_m2l_lane<12>", 1 << 27, 0.6): {
-        "sources_sha256": "ab7fb94fdcf701d71b6636f8be950a39e390edd137c367607f90ea5215d786a1",
+        "sources_sha256": "d60aa9ee5514561961c9a729f76b955f552780857c530ae7a53454ac798d4af6",
         "fetch_kib": 3976133030.875,
         "write_kib": 479565723.84375,
     },

@@ -146,8 +146,8 @@ __device__ __forceinline__ void japply_mf(float* X, const float* tab, int lane) 
     constexpr bool two = n2 > n;
     constexpr int s2 = two ? lops::cls_size(n2, 0) : 0, s3 = two ? lops::cls_size(n2, 1) : 0;
     blocks_mf<lops::cls_size(n, 0), lops::j_offset(n, 0), lops::cls_size(n, 1), lops::j_offset(n, 1), s2,
-              lops::j_offset(n2, 0), s3, lops::j_offset(n2, 1)>(X, tab, tab, tab, tab, lane, JIn<n, 0>{}, JIn<n, 1>{}, JIn<n2, 0>{},
-                                     JIn<n2, 1>{});
+              lops::j_offset(n2, 0), s3, lops::j_offset(n2, 1)>(X, tab, tab, tab, tab, lane, JIn<n, 0>{},
+                                                                  JIn<n, 1>{}, JIn<n2, 0>{}, JIn<n2, 1>{});
     // a few blocks at a time: bounded registers
     __builtin_amdgcn_sched_barrier(0);
   });
@@ -212,10 +212,10 @@ __device__ __forceinline__ void ztrans_mf(float* X, const float* tab, int lane, 
   }
 }
 
-// One halving exchange of the sum over the lanes: dst[i] = src[i] of this
-// lane and of its partner at lane distance D (lanes with bit D clear) or
-// src[NS/2 + i] of both (bit set); the upper half of an odd count is padded
-// with zero.  Distances 32 and 16 are permlane swaps (the swap of (lower,
+// One halving exchange of the sum over the lanes, ND = ceil(NS / 2): dst[i]
+// = src[i] of this lane and of its partner at lane distance D (lanes with
+// bit D clear) or src[ND + i] of both (bit set); the upper half of an odd
+// count is padded with zero.  Distances 32 and 16 are permlane swaps (the swap of (lower,
 // upper) leaves each lane the two terms of its own sum), 8, 2 and 1 a DPP
 // read of the partner, 4 two DPP shifts.
 template <int CTRL>
