@@ -57,7 +57,7 @@ M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", 
         "write_kib": 479565723.84375,
     },
     ("k_m2l_quad<12>", 1 << 27, 0.6): {
-        "sources_sha256": "ab6b2503ac03601fcc581788abd34db077d20876357df5a7230159c354e491b0",
+        "sources_sha256": "edb2eb605b7307e8ab5177ba251be9110370620356fe5905ef23a764bd6ab178",
         "fetch_kib": 10546731641.875,
         "write_kib": 17000206.6875,
     },

@@ -52,7 +52,7 @@ __host__ __device__ constexpr int qlvl(int nt, int s) {
   return v;
 }
 
-// degree and block of register R
+// degree of register R
 __host__ __device__ constexpr int qdeg(int R) {
   int d = 0;
   while (lops::qbase(d + 1, 0) <= R) ++d;
@@ -217,9 +217,10 @@ __device__ __forceinline__ int qlevel_of(const LevelView& lv, int64_t gid) {
   return l;
 }
 
-// Waves per SIMD: 2 up to order 13, 1 from 16 on.  One block per CU (512 threads
-// for two waves per SIMD, 256 for one), so that the tables (J, J^T and the z
-// core: 55 KB at order 12, 158 KB at 18) are staged into LDS once per CU.
+// Waves per SIMD: 2 up to order 13, 1 from 16 on.  One block per CU (512
+// threads for two waves per SIMD, 256 for one), so that the tables (J, J^T
+// and the z core: 55 KB at order 12, 158 KB at 18) are staged into LDS once
+// per CU.
 template <int P>
 struct QuadCfg {
   static constexpr int kWaves = P <= 13 ? 2 : 1;
@@ -230,7 +231,8 @@ struct QuadCfg {
 };
 
 template <int P>
-__global__ __launch_bounds__(QuadCfg<P>::kThreads) __attribute__((amdgpu_waves_per_eu(QuadCfg<P>::kWaves, QuadCfg<P>::kWaves))) void
+__global__ __launch_bounds__(QuadCfg<P>::kThreads)
+__attribute__((amdgpu_waves_per_eu(QuadCfg<P>::kWaves, QuadCfg<P>::kWaves))) void
 k_m2l_quad(LevelView lv, const double* __restrict__ qtab, const int* __restrict__ pos, int S,
            const double* __restrict__ Mq, double* __restrict__ Lx, int64_t ntarget, const int32_t* __restrict__ order,
            int* __restrict__ queue) {
@@ -408,7 +410,8 @@ void launch_one_quad(const Tree& t, const Tables& tb, const double* Mx, double* 
   int* queue = (int*)dalloc(sizeof(int), s);
   k_zero_queue_q<<<1, 64, 0, s>>>(queue);
   HIPCHECK(hipGetLastError());
-  k_m2l_quad<P><<<grid, QuadCfg<P>::kThreads, 0, s>>>(t.view(), tb.quad, tb.pos, tb.stride, Mq, Lx, ntarget, t.m2l_order, queue);
+  k_m2l_quad<P><<<grid, QuadCfg<P>::kThreads, 0, s>>>(t.view(), tb.quad, tb.pos, tb.stride, Mq, Lx, ntarget,
+                                                       t.m2l_order, queue);
   HIPCHECK(hipGetLastError());
   dfree(queue, s);
   dfree(Mq, s);
