@@ -37,8 +37,8 @@ LANE_M2L_MAX_P = 14            # mixed precision: the per-lane M2L kernel up to 
 
 def quad_m2l(p: int) -> bool:
     """binary64 M2L runs four lanes per pair at these orders (16x16 tiles at
-    14 and 15, the vector kernel above 18)"""
-    return p <= 13 or 16 <= p <= 18
+    14 and 15)"""
+    return p <= 13 or 16 <= p <= 20
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one M2L launch, per kernel and workload: from two rocprofv3
@@ -52,12 +52,12 @@ COPY_WRITE_SCALE = 1.0
 M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
     # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12): mixed precision and binary64
     ("k_m2l_lane<12>", 1 << 27, 0.6): {
-        "sources_sha256": "d60aa9ee5514561961c9a729f76b955f552780857c530ae7a53454ac798d4af6",
+        "sources_sha256": "a4cb93d50b888a17f4ead6f5848230b3a4f963511714ec6e3a8103966f7b4705",
         "fetch_kib": 3976133030.875,
         "write_kib": 479565723.84375,
     },
     ("k_m2l_quad<12>", 1 << 27, 0.6): {
-        "sources_sha256": "edb2eb605b7307e8ab5177ba251be9110370620356fe5905ef23a764bd6ab178",
+        "sources_sha256": "e02200a47f9a5f2a0feb0d3dbdf98e56e552908bea1938538c7008547c9eb57f",
         "fetch_kib": 10546731641.875,
         "write_kib": 17000206.6875,
     },
@@ -253,11 +253,9 @@ def timed_leg(X, Y, Z, Q, L, theta, p, prec, outs, steps, warmup, stream, torch)
         kernel, bound, peak = f"k_m2l_lane<{p}>", "mfma", FP32_MFMA_PEAK_TFLOPS
     elif not mixed and quad_m2l(p):
         kernel, bound, peak = f"k_m2l_quad<{p}>", "mfma", FP64_PEAK_TFLOPS
-    elif p <= 15:
+    else:
         kernel = f"k_m2l_mfma<{p}, {'float' if mixed else 'double'}>"
         bound, peak = "mfma", FP32_MFMA_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
-    else:
-        kernel, bound, peak = "k_m2l", "alu", FP64_PEAK_TFLOPS
     roofline = {
         "kernel": kernel, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4), "traffic": m2l_traffic_gb(kernel, n, theta),

@@ -330,12 +330,13 @@ std::vector<float> lane_tables(const HostTables& h, int p) {
   return out;
 }
 
-// The operands of the binary64 per-quad M2L kernel (lane_ops.h): J and J^T
-// as 4x4 parts in instruction order, then the z-translation core.
+// The operands of the binary64 per-quad M2L kernel (lane_ops.h): J and, where
+// it fits, J^T as 4x4 parts in instruction order, then the z-translation core.
 std::vector<double> quad_tables(const HostTables& h, int p) {
   using namespace lops;
   std::vector<double> out((size_t)qtable_doubles(p), 0.0);
-  for (int trans = 0; trans < 2; ++trans) {
+  const int ntab = qtable_has_jt(p) ? 2 : 1;
+  for (int trans = 0; trans < ntab; ++trans) {
     double* T = out.data() + (size_t)trans * 16 * qj_count(p);
     for (int d = 0; d <= p; ++d) {
       const int sd = 2 * d + 1, nr = qreg(d);
@@ -352,7 +353,7 @@ std::vector<double> quad_tables(const HostTables& h, int p) {
           }
     }
   }
-  double* Z = out.data() + (size_t)2 * 16 * qj_count(p);
+  double* Z = out.data() + (size_t)ntab * 16 * qj_count(p);
   const size_t P1 = (size_t)p + 1;
   for (int m = 0; m <= p; ++m)
     for (int d = m; d <= p; ++d)
@@ -402,7 +403,6 @@ const Tables& tables_for(int p, hipStream_t s) {
   t.p = p;
   t.J = upload(h.J, s);
   t.joff = upload(h.joff, s);
-  t.A = upload(h.A, s);
   t.B = upload(h.B, s);
   t.rc = upload(h.rc, s);
   t.stride = h.stride;
@@ -435,14 +435,13 @@ struct XT {
   const int* __restrict__ ipos;
   const double* __restrict__ J;
   const int* __restrict__ joff;
-  const double* __restrict__ A;
   const double* __restrict__ B;
   const double* __restrict__ rc;
 };
 
-XT make_xt(const Tables& t) { return XT{t.p, nterms(t.p), t.stride, t.pos, t.ipos, t.J, t.joff, t.A, t.B, t.rc}; }
+XT make_xt(const Tables& t) { return XT{t.p, nterms(t.p), t.stride, t.pos, t.ipos, t.J, t.joff, t.B, t.rc}; }
 
-enum Kind { kM2M = 0, kM2L = 1, kL2L = 2 };
+enum Kind { kM2M = 0, kL2L = 2 };
 
 __device__ __forceinline__ void decode(int k, int& n, int& i) {
   n = (int)sqrtf((float)k);
@@ -455,7 +454,7 @@ __device__ __forceinline__ void decode(int k, int& n, int& i) {
 struct XScratch {
   double ca[kMaxOrder + 1], sa[kMaxOrder + 1];  // cos/sin(m alpha)
   double cb[kMaxOrder + 1], sb[kMaxOrder + 1];  // cos/sin(m beta)
-  double pw[2 * kMaxOrder + 2];                 // rho^-k (M2L) or rho^k (M2M, L2L)
+  double pw[2 * kMaxOrder + 2];                 // rho^k
 };
 
 // dst = Rz(sign * gamma) src   (per (c_m, s_m) pair)
@@ -508,11 +507,7 @@ __device__ __forceinline__ void ztrans(const double* src, double* dst, const XT&
     const int m = (i + 1) >> 1;
     const int t = (i == 0) ? 0 : ((i & 1) ? 0 : 1);
     double acc = 0.0;
-    if (kind == kM2L) {
-      const double* Ar = tb.A + ((size_t)m * P1 + d) * P1;
-      for (int n = m; n <= p; ++n) acc += Ar[n] * (pw[n] * src[cidx(n, m, t)]);
-      acc *= pw[d + 1];
-    } else if (kind == kM2M) {
+    if (kind == kM2M) {
       const double* Br = tb.B + ((size_t)m * P1 + d) * P1;
       for (int j = m; j <= d; ++j) acc += Br[j] * (pw[d - j] * src[cidx(j, m, t)]);
     } else {
@@ -522,16 +517,16 @@ __device__ __forceinline__ void ztrans(const double* src, double* dst, const XT&
   }
 }
 
-// acc += T(d) X for one translation of the given kind, d = (dx, dy, dz):
-//   M2L: d = source centre - target centre; M2M, L2L: d = child - parent.
-// X is overwritten.  Called by a whole 64-lane workgroup.
+// acc += T(d) X for one M2M or L2L translation, d = (dx, dy, dz) = child
+// centre - parent centre.  X is overwritten.  Called by a whole 64-lane
+// workgroup.
 __device__ void translate(int kind, double dx, double dy, double dz, double* X, double* T, double* acc,
                           const XT& tb, XScratch& sc) {
   const int lane = threadIdx.x & 63;
   const int nt = tb.nt, p = tb.p;
   const double rxy2 = dx * dx + dy * dy;
   const double rho2 = rxy2 + dz * dz;
-  if (rho2 == 0.0) {  // coincident centres: identity (never for M2L)
+  if (rho2 == 0.0) {  // coincident centres: identity
     for (int k = lane; k < nt; k += 64) acc[k] += X[k];
     __syncthreads();
     return;
@@ -555,9 +550,8 @@ __device__ void translate(int kind, double dx, double dy, double dz, double* X, 
     sc.sb[lane] = s2;
   }
   if (lane <= 2 * p + 1) {
-    const double base = kind == kM2L ? 1.0 / rho : rho;
     double v = 1.0;
-    for (int q = 0; q < lane; ++q) v *= base;
+    for (int q = 0; q < lane; ++q) v *= rho;
     sc.pw[lane] = v;
   }
   __syncthreads();
@@ -609,31 +603,6 @@ __device__ __forceinline__ int level_of(const LevelView& lv, int64_t gid) {
   int l = 0;
   while (l < lv.L && gid >= lv.gofs[l + 1]) ++l;
   return l;
-}
-
-// ---- M2L: one 64-lane workgroup per target box of levels 1..L ----
-__global__ __launch_bounds__(64) void k_m2l(LevelView lv, XT tb, const double* __restrict__ Mx,
-                                            double* __restrict__ Lx) {
-  __shared__ double X[kNtMax], T[kNtMax], acc[kNtMax];
-  __shared__ XScratch sc;
-  const int lane = threadIdx.x;
-  const int nt = tb.nt;
-  const int64_t gid = lv.gofs[1] + blockIdx.x;
-  const int l = level_of(lv, gid);
-  const int64_t i = gid - lv.gofs[l];
-  for (int k = lane; k < nt; k += 64) acc[k] = 0.0;
-  const double* gi = lv.geom[l] + i * 10;
-  const double cix = gi[6], ciy = gi[7], ciz = gi[8];
-  const int64_t e0 = lv.w_off[l][i], e1 = lv.w_off[l][i + 1];
-  for (int64_t e = e0; e < e1; ++e) {
-    const int64_t j = lv.w_idx[l][e];
-    const double* gj = lv.geom[l] + j * 10;
-    load_coefs(Mx + (size_t)(lv.gofs[l] + j) * tb.stride, X, tb);
-    __syncthreads();
-    translate(kM2L, gj[6] - cix, gj[7] - ciy, gj[8] - ciz, X, T, acc, tb, sc);
-  }
-  __syncthreads();
-  store_coefs(acc, Lx + (size_t)gid * tb.stride, tb);
 }
 
 // ---- M2M: parents of level l-1 from their 8 children on level l ----
@@ -841,18 +810,15 @@ bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* 
 bool launch_m2l_mfma_mixed(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
 bool launch_m2l_quad64(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
 
-// M2L on the matrix cores for p <= 15 (binary64, or binary32 on scaled
-// expansions for FMM_PREC_MIXED), else the binary64 kernel above
+// M2L on the matrix cores: binary32 on scaled expansions for orders up to 15
+// unless binary64 is asked for (one pair per lane up to 14, 16-pair tiles at
+// 15), else binary64 (four lanes per pair at orders up to 13 and 16..20,
+// 16-pair tiles at 14 and 15)
 void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, int prec, hipStream_t s) {
-  // binary32 (orders up to 15), else binary64: four lanes per pair on the
-  // matrix cores (orders up to 13 and 16..18), 16-pair tiles (14, 15), the
-  // vector kernel above
   if (prec != FMM_PREC_F64 && launch_m2l_mfma_mixed(t, tb, Mx, Lx, s)) return;
   if (launch_m2l_quad64(t, tb, Mx, Lx, s)) return;
   if (launch_m2l_mfma(t, tb, Mx, Lx, s)) return;
-  const int64_t nb = t.nbox_total - 1;
-  k_m2l<<<(unsigned)nb, 64, 0, s>>>(t.view(), make_xt(tb), Mx, Lx);
-  HIPCHECK(hipGetLastError());
+  fail(FMM_EUNSUPPORTED, "no M2L kernel for order " + std::to_string(tb.p));
 }
 void launch_l2l(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s) {
   k_l2l<<<(unsigned)t.lev[l].nbox, 64, 0, s>>>(t.view(), l, make_xt(tb), Lx);

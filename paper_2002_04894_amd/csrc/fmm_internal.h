@@ -135,7 +135,6 @@ struct Tables {
   int p = -1;
   double* J = nullptr;     // per degree n a (2n+1)^2 row-major block at joff[n]
   int* joff = nullptr;     // p + 2 offsets
-  double* A = nullptr;     // M2L along z: A[(m*(p+1) + j)*(p+1) + n]
   double* B = nullptr;     // M2M / L2L along z: B[(m*(p+1) + n)*(p+1) + j]
   double* rc = nullptr;    // recurrence constants, see expansions.hip
   // storage of one expansion: `stride` doubles per box; coefficient k
@@ -153,8 +152,8 @@ struct Tables {
   // J, J^T and the z-translation core as operands of the per-lane M2L
   // kernel's 4x4x1 matrix instructions (lane_ops.h), binary32
   float* lane = nullptr;
-  // J, J^T and the z-translation core for the binary64 per-quad M2L kernel
-  // (lane_ops.h)
+  // J, J^T (where it fits in LDS) and the z-translation core for the
+  // binary64 per-quad M2L kernel (lane_ops.h)
   double* quad = nullptr;
   bool tiled = false;
 };

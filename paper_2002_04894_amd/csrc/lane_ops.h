@@ -92,10 +92,19 @@ __host__ __device__ constexpr int qj_offset(int d, int x) {
   return u + x * qreg(d) * qreg(d);
 }
 __host__ __device__ constexpr int qj_count(int p) { return qj_offset(p + 1, 0); }
-// table: J, J^T (16 values per instruction each), then the z-translation core
-// A[m][d][n] for m = 0 .. p + 1 (order p + 1 all zero: the slot of the lanes
-// whose order exceeds p)
-__host__ __device__ constexpr int qtable_doubles(int p) { return 2 * 16 * qj_count(p) + (p + 2) * (p + 1) * (p + 1); }
+// z-translation core A[m][d][n] for m = 0 .. p + 1 (order p + 1 all zero: the
+// slot of the lanes whose order exceeds p)
+__host__ __device__ constexpr int qcore_doubles(int p) { return (p + 2) * (p + 1) * (p + 1); }
+// whether the table holds J^T beside J: where both fit in 160 KB of LDS with
+// the core (orders up to 18); above, the kernel reads J^T from J transposed
+__host__ __device__ constexpr bool qtable_has_jt(int p) {
+  return (2 * 16 * qj_count(p) + qcore_doubles(p)) * 8 <= 160 * 1024;
+}
+// table: J (16 values per instruction), J^T in the same form if it fits, then
+// the z-translation core
+__host__ __device__ constexpr int qtable_doubles(int p) {
+  return (qtable_has_jt(p) ? 2 : 1) * 16 * qj_count(p) + qcore_doubles(p);
+}
 
 }  // namespace lops
 }  // namespace fmm

@@ -5,7 +5,7 @@
 // Every lane of a wave takes one pair of the same target box, 64 pairs at a
 // time, and holds its pair's whole expansion in registers in the standard
 // order (c_{n,0}, c_{n,1}, s_{n,1}, ..., per degree n).  The translation is
-// the same sequence as the binary64 vector kernel k_m2l:
+// the same sequence as in the binary64 kernels:
 //   Rz(-beta), J^T, Rz(-alpha), J, z-axis translation, J^T, Rz(alpha), J, Rz(beta),
 // with J the fixed quarter turn about x (block-diagonal in two parity classes
 // per degree) and (alpha, beta) the polar and azimuthal angles of

@@ -17,7 +17,9 @@
 //     lanes of a pair, and its output row i lands in phase i of the same pair,
 //     so every step's result is the next step's operand in place; the
 //     operator values come from LDS (binary64 instructions take no broadcast
-//     of one block's operand, so every lane reads its value);
+//     of one block's operand, so every lane reads its value); J^T has a
+//     table of its own up to order 18 and above reads the table of J with
+//     the two chunk indices swapped and each 4x4 part transposed;
 //   - a z-turn multiplies the (cosine, sine) parts of (d, m), which share a
 //     lane and register, by the lane's own e^{i m theta};
 //   - the z translation of order m involves only order-m coefficients of
@@ -26,7 +28,7 @@
 //   - the 16 pair results are summed across the lanes by halving exchanges
 //     (fixed order: deterministic) and the batches in binary64.
 // Padding is per 4x4 part of a block: 1.57x the algorithmic J products at
-// order 12, against 2.42x for the 16x16 tiles of m2l_mfma.hip.  Orders 16..18
+// order 12, against 2.42x for the 16x16 tiles of m2l_mfma.hip.  Orders 16..20
 // run here too (one wave per SIMD), where the tiles stop.
 #include <type_traits>
 
@@ -64,7 +66,9 @@ __device__ __forceinline__ double mfma64(double a, double b, double c) {
 }
 
 // One block (d, x) of a J application: NR = qreg(d) k-steps times NR output
-// chunks; tl = the lane's slot in a 16-value operand (4 k + i)
+// chunks; tl = the lane's slot in a 16-value operand, 4 k + i, or with T
+// (J^T from the table of J, whose part (c, g) transposed is part (g, c) of
+// J^T) 4 i + k
 template <int D, int X>
 struct QBlk {
   static constexpr int NR = lops::qreg(D);
@@ -74,12 +78,13 @@ struct QBlk {
   __device__ __forceinline__ QBlk() {
     qfor<0, NR>([&](auto c) __attribute__((always_inline)) { acc[c] = 0.0; });
   }
-  template <int G>
+  template <bool T, int G>
   __device__ __forceinline__ void step(const double* X_, const double* tab, int tl) {
     if constexpr (G < NR) {
       const double xg = X_[R0 + G];
       qfor<0, NR>([&](auto c) __attribute__((always_inline)) {
-        constexpr int u = U0 + G * NR + decltype(c)::value;
+        constexpr int C = decltype(c)::value;
+        constexpr int u = U0 + (T ? C * NR + G : G * NR + C);
         acc[c] = mfma64(tab[16 * u + tl], xg, acc[c]);
       });
     }
@@ -89,9 +94,10 @@ struct QBlk {
   }
 };
 
-// X <- J X (or J^T X, with that table): degree d beside degree P - d, both
-// blocks each, in lock-step over the k-steps (independent chains in flight)
-template <int P>
+// X <- J X (or J^T X from its own table; T: J^T X from the table of J, tl the
+// lane's slot for that case): degree d beside degree P - d, both blocks each,
+// in lock-step over the k-steps (independent chains in flight)
+template <int P, bool T>
 __device__ __forceinline__ void qjapply(double* X, const double* tab, int tl) {
   qfor<0, P / 2 + 1>([&](auto dI) __attribute__((always_inline)) {
     constexpr int d = decltype(dI)::value, d2 = P - d;
@@ -102,18 +108,18 @@ __device__ __forceinline__ void qjapply(double* X, const double* tab, int tl) {
       QBlk<d2, 1> b1;
       qfor<0, lops::qreg(d2)>([&](auto g) __attribute__((always_inline)) {
         constexpr int G = decltype(g)::value;
-        a0.template step<G>(X, tab, tl);
-        a1.template step<G>(X, tab, tl);
-        b0.template step<G>(X, tab, tl);
-        b1.template step<G>(X, tab, tl);
+        a0.template step<T, G>(X, tab, tl);
+        a1.template step<T, G>(X, tab, tl);
+        b0.template step<T, G>(X, tab, tl);
+        b1.template step<T, G>(X, tab, tl);
       });
       b0.store(X);
       b1.store(X);
     } else {
       qfor<0, lops::qreg(d)>([&](auto g) __attribute__((always_inline)) {
         constexpr int G = decltype(g)::value;
-        a0.template step<G>(X, tab, tl);
-        a1.template step<G>(X, tab, tl);
+        a0.template step<T, G>(X, tab, tl);
+        a1.template step<T, G>(X, tab, tl);
       });
     }
     a0.store(X);
@@ -218,14 +224,14 @@ __device__ __forceinline__ int qlevel_of(const LevelView& lv, int64_t gid) {
 }
 
 // Waves per SIMD: 2 up to order 13, 1 from 16 on.  One block per CU (512
-// threads for two waves per SIMD, 256 for one), so that the tables (J, J^T
-// and the z core: 55 KB at order 12, 158 KB at 18) are staged into LDS once
-// per CU.
+// threads for two waves per SIMD, 256 for one), so that the tables (J, J^T up
+// to order 18, the z core: 55 KB at order 12, 158 KB at 18, 143 KB at 20) are
+// staged into LDS once per CU.
 template <int P>
 struct QuadCfg {
   static constexpr int kWaves = P <= 13 ? 2 : 1;
   static constexpr int kThreads = 256 * kWaves;
-  static constexpr int kJ = 16 * lops::qj_count(P);  // doubles per J table
+  static constexpr int kJ = 16 * lops::qj_count(P);  // doubles of the J table
   static constexpr int kLds = lops::qtable_doubles(P);
   static_assert(kLds * 8 <= 160 * 1024, "the tables must fit in LDS");
 };
@@ -243,10 +249,12 @@ k_m2l_quad(LevelView lv, const double* __restrict__ qtab, const int* __restrict_
   __shared__ double tabs[NL];
   for (int i = threadIdx.x; i < NL; i += blockDim.x) tabs[i] = qtab[i];
   __syncthreads();
-  const double* Az = tabs + 2 * NJ;
+  constexpr bool HJT = lops::qtable_has_jt(P);
+  const double* Az = tabs + (HJT ? 2 : 1) * NJ;
   const int lane = threadIdx.x & 63;
   const int k = lane >> 4, q = lane & 15;
-  const int tl = 4 * k + (lane & 3);  // this lane's value in a 4x4 operand part
+  const int tl = 4 * k + (lane & 3);   // this lane's value in a 4x4 part of J
+  const int tlt = 4 * (lane & 3) + k;  // and of J^T
   for (;;) {
     int kq = 0;
     if (lane == 0) kq = atomicAdd(queue, 1);
@@ -290,13 +298,13 @@ k_m2l_quad(LevelView lv, const double* __restrict__ qtab, const int* __restrict_
   x;                 \
   __builtin_amdgcn_sched_barrier(0)
       FMM_QSTEP(qrotz<P>(X, cb, sb, -1.0, k));
-      FMM_QSTEP(qjapply<P>(X, tabs + NJ, tl));
+      FMM_QSTEP((qjapply<P, !HJT>(X, HJT ? tabs + NJ : tabs, HJT ? tl : tlt)));
       FMM_QSTEP(qrotz<P>(X, ca, sa, -1.0, k));
-      FMM_QSTEP(qjapply<P>(X, tabs, tl));
+      FMM_QSTEP((qjapply<P, false>(X, tabs, tl)));
       FMM_QSTEP(qztrans<P>(X, Az, k, in_base, out_base, out_mult));
-      FMM_QSTEP(qjapply<P>(X, tabs + NJ, tl));
+      FMM_QSTEP((qjapply<P, !HJT>(X, HJT ? tabs + NJ : tabs, HJT ? tl : tlt)));
       FMM_QSTEP(qrotz<P>(X, ca, sa, 1.0, k));
-      FMM_QSTEP(qjapply<P>(X, tabs, tl));
+      FMM_QSTEP((qjapply<P, false>(X, tabs, tl)));
       FMM_QSTEP(qrotz<P>(X, cb, sb, 1.0, k));
 #undef FMM_QSTEP
 
@@ -419,9 +427,9 @@ void launch_one_quad(const Tree& t, const Tables& tb, const double* Mx, double* 
 
 }  // namespace
 
-// binary64 M2L with this kernel: orders up to 13 and 16..18; false for the
-// others (14 and 15: the 16x16 tile kernel is faster, the two-wave quad
-// kernel spills; above 18 its tables no longer fit in LDS)
+// binary64 M2L with this kernel: orders up to 13 and 16..20; false for 14
+// and 15 (the 16x16 tile kernel is faster there, the two-wave quad kernel
+// spills)
 bool launch_m2l_quad64(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s) {
   switch (tb.p) {
     case 0: launch_one_quad<0>(t, tb, Mx, Lx, s); break;
@@ -441,6 +449,8 @@ bool launch_m2l_quad64(const Tree& t, const Tables& tb, const double* Mx, double
     case 16: launch_one_quad<16>(t, tb, Mx, Lx, s); break;
     case 17: launch_one_quad<17>(t, tb, Mx, Lx, s); break;
     case 18: launch_one_quad<18>(t, tb, Mx, Lx, s); break;
+    case 19: launch_one_quad<19>(t, tb, Mx, Lx, s); break;
+    case 20: launch_one_quad<20>(t, tb, Mx, Lx, s); break;
     default: return false;
   }
   return true;

@@ -597,11 +597,11 @@ size_t eval_scratch_bytes(const Tree& t, int p, int prec) {
     const size_t far = t.L >= 1 ? 4 * (size_t)std::max<int64_t>(1, npts) * 8 : 0;
     // the M2L kernel's own copy of the multipoles, per box: binary32 dense
     // (per-lane kernel, orders up to 14) or tiled (order 15), else binary64
-    // in the quad layout (orders up to 13 and 16..18)
+    // in the quad layout (orders up to 13 and 16..20)
     size_t copy = 0;
     if (prec != FMM_PREC_F64 && p <= 14) copy = (size_t)lops::dense_stride(p) * 4;
     else if (prec != FMM_PREC_F64 && p <= tl::kMaxP) copy = stride * 4;
-    else if (p <= 13 || (p >= 16 && p <= 18)) copy = (size_t)lops::nq(p) * 4 * 8;
+    else if (p <= 13 || p >= 16) copy = (size_t)lops::nq(p) * 4 * 8;
     size_t expn = 0;
     if (t.L >= 1) expn = 2 * nbox * stride * 8 + 256 + nbox * copy;  // multipoles, locals, M2L queue, copy
     const size_t part = (size_t)std::max<int64_t>(0, npart) * 32;

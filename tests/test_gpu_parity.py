@@ -276,11 +276,12 @@ def test_full_size_gmix1m_sampled(torch, F, orc):
     gt.free()
 
 
-@pytest.mark.parametrize("p,L", [(17, 2), (18, 2), (20, 2)])
-def test_parity_binary64_above_mfma_orders(torch, F, orc, p, L):
-    """Orders above 15 run M2L on the binary64 VALU kernel: with weak pairs,
-    M2M and L2L against the oracle."""
-    say(f"[valu] p={p} L={L}")
+@pytest.mark.parametrize("p,L", [(16, 2), (17, 2), (18, 2), (19, 2), (20, 2)])
+def test_parity_binary64_orders_16_to_20(torch, F, orc, p, L):
+    """Orders above 15 run M2L four lanes per pair in binary64 (one wave per
+    SIMD, J and its transpose from one table): with weak pairs, M2M and L2L
+    against the oracle."""
+    say(f"[quad] p={p} L={L}")
     x, y, z, q = make("gmix", 3000, seed=p)
     ot = orc.Tree(x, y, z, L, 0.5)
     assert ot.lists(L, 1)[1].size > 0
