@@ -34,6 +34,16 @@ __device__ __forceinline__ bool is_weak(const double* gi, double cjx, double cjy
 // geometry loads are issued before any of them is tested.
 constexpr int kListGroups = 4;
 
+// A block takes four consecutive boxes.  Blocks are dispatched to the eight
+// XCDs in turn; they are mapped to box groups so that each XCD takes a
+// contiguous run of groups in tree order, whose candidates (children of
+// nearby parents' strong lists) overlap and stay in that XCD's L2.  The grid
+// is 8 ceil(ngroup / 8) blocks; indexes past the last group return.
+__device__ __forceinline__ int64_t xcd_box(int64_t nbox) {
+  const int64_t per = ((nbox + 3) / 4 + 7) / 8;
+  return 4 * ((int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8) + (threadIdx.x >> 6);
+}
+
 // Candidate centre and radius as one 32-byte record per box (one load per
 // candidate instead of four at the 80-byte stride of the box geometry).
 __global__ void k_centre_radius(int64_t nbox, const double* __restrict__ geom, double4* __restrict__ cr) {
@@ -60,7 +70,7 @@ __global__ __launch_bounds__(256) void k_lists_count(int64_t nbox, const double*
                                                      uint64_t* __restrict__ mask, int32_t* __restrict__ ns,
                                                      int32_t* __restrict__ nw) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = xcd_box(nbox);
   if (i >= nbox) return;
   const int64_t par = i >> 3;
   const double* gi = geom + i * 10;
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(256) void k_lists_fill(int64_t nbox, const int64_t*
                                                     const int64_t* __restrict__ s_off, int32_t* __restrict__ s_idx,
                                                     const int64_t* __restrict__ w_off, int32_t* __restrict__ w_idx) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = xcd_box(nbox);
   if (i >= nbox) return;
   const int64_t par = i >> 3;
   const int64_t e0 = ps_off[par];
@@ -304,7 +314,7 @@ void lists_build(Tree& t, hipStream_t s) {
     // entries) + 8 npar, known on the host without a read-back
     const int64_t nwords = P.s_nnz + 8 * npar;
     uint64_t* mask = (uint64_t*)dalloc(std::max<int64_t>(1, nwords) * sizeof(uint64_t), s);
-    const unsigned grid = (unsigned)((nb + 3) / 4);
+    const unsigned grid = (unsigned)(8 * (((nb + 3) / 4 + 7) / 8));
     k_lists_count<<<grid, 256, 0, s>>>(nb, V.geom, cr, P.s_off, P.s_idx, t.theta, wofs, words, mask, ns, nw);
     HIPCHECK(hipGetLastError());
     V.s_off = (int64_t*)dalloc((nb + 1) * sizeof(int64_t), s);
