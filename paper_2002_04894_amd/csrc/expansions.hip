@@ -642,10 +642,19 @@ __global__ __launch_bounds__(64) void k_l2l(LevelView lv, int l, XT tb, double* 
 }
 
 // ---- P2M: one 64-lane workgroup per leaf, lanes over points ----
+// For each order m every lane puts its point's terms of degrees m..p (cosine
+// and sine parts: the columns) into one LDS row; then each column is summed
+// over the 64 rows in a fixed order, by one lane (more than 32 columns) or by
+// two lanes of 32 rows each whose halves are then added.  The row stride
+// p2m_stride(p) is odd, so the row writes and the column reads are free of
+// bank conflicts.
+__host__ __device__ constexpr int p2m_stride(int p) { return 2 * (p + 1) + 1; }
+
 __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* __restrict__ px,
                                             const double* __restrict__ py, const double* __restrict__ pz,
                                             const double* __restrict__ qt, double* __restrict__ Mx) {
   __shared__ double acc[kNtMax];
+  extern __shared__ double rows[];  // 64 x p2m_stride(p)
   const int lane = threadIdx.x;
   const int L = lv.L, p = tb.p, P1 = p + 1, nt = tb.nt;
   const int64_t b = blockIdx.x;
@@ -659,6 +668,8 @@ __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* _
   const double* c1 = tb.rc + 2 * P1;
   const double* c2 = tb.rc + 2 * P1 + P1 * P1;
   const double s2 = 1.4142135623730951;
+  const int SP = p2m_stride(p);
+  double* row = rows + lane * SP;
   for (int c0 = s0; c0 < s1; c0 += 64) {
     const int t = c0 + lane;
     const bool valid = t < s1;
@@ -694,18 +705,22 @@ __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* _
           g1r = gr;
           g1i = gi;
         }
-        double vc = (m == 0 ? 1.0 : s2) * q * gr;
-        double vs = s2 * q * gi;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          vc += __shfl_xor(vc, d);
-          vs += __shfl_xor(vs, d);
-        }
-        if (lane == 0) {
-          acc[cidx(n, m, 0)] += vc;
-          if (m > 0) acc[cidx(n, m, 1)] += vs;
-        }
+        row[2 * (n - m)] = (m == 0 ? 1.0 : s2) * q * gr;
+        row[2 * (n - m) + 1] = s2 * q * gi;
       }
+      __syncthreads();
+      // column col = 2 (n - m) + part of every row
+      const int ncol = 2 * (P1 - m);
+      const bool two = ncol <= 32;
+      const int col = two ? lane >> 1 : lane;
+      const int r0 = two ? 32 * (lane & 1) : 0, nr = two ? 32 : 64;
+      double v = 0.0;
+      if (col < ncol)
+        for (int r = r0; r < r0 + nr; ++r) v += rows[r * SP + col];
+      if (two) v += __shfl_xor(v, 1);
+      const int n = m + (col >> 1), part = col & 1;
+      if (col < ncol && (!two || (lane & 1) == 0) && (m > 0 || part == 0)) acc[cidx(n, m, part)] += v;
+      __syncthreads();
     }
   }
   __syncthreads();
@@ -799,7 +814,8 @@ __global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const int32_t* 
 
 // launch helpers used by evaluate() (p2p.hip)
 void launch_p2m(const Tree& t, const Tables& tb, const double* qt, double* Mx, hipStream_t s) {
-  k_p2m<<<(unsigned)t.lev[t.L].nbox, 64, 0, s>>>(t.view(), make_xt(tb), t.px, t.py, t.pz, qt, Mx);
+  const size_t lds = (size_t)64 * p2m_stride(tb.p) * sizeof(double);
+  k_p2m<<<(unsigned)t.lev[t.L].nbox, 64, lds, s>>>(t.view(), make_xt(tb), t.px, t.py, t.pz, qt, Mx);
   HIPCHECK(hipGetLastError());
 }
 void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s) {

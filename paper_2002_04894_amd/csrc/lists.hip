@@ -34,14 +34,14 @@ __device__ __forceinline__ bool is_weak(const double* gi, double cjx, double cjy
 // geometry loads are issued before any of them is tested.
 constexpr int kListGroups = 4;
 
-// A block takes four consecutive boxes.  Blocks are dispatched to the eight
-// XCDs in turn; they are mapped to box groups so that each XCD takes a
-// contiguous run of groups in tree order, whose candidates (children of
-// nearby parents' strong lists) overlap and stay in that XCD's L2.  The grid
-// is 8 ceil(ngroup / 8) blocks; indexes past the last group return.
+// A block (one wave) takes one box.  Blocks are dispatched to the eight XCDs
+// in turn; they are mapped to boxes so that each XCD takes a contiguous run
+// of boxes in tree order, whose candidates (children of nearby parents'
+// strong lists) overlap and stay in that XCD's L2.  The grid is
+// 8 ceil(nbox / 8) blocks; indexes past the last box return.
 __device__ __forceinline__ int64_t xcd_box(int64_t nbox) {
-  const int64_t per = ((nbox + 3) / 4 + 7) / 8;
-  return 4 * ((int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8) + (threadIdx.x >> 6);
+  const int64_t per = (nbox + 7) / 8;
+  return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
 // Candidate centre and radius as one 32-byte record per box (one load per
@@ -61,7 +61,7 @@ __global__ void k_mask_words(int64_t npar, const int64_t* __restrict__ ps_off, i
 // of each group of 64 candidates is kept as one mask word (box i's words
 // start at 8 wofs[parent] + child * words[parent]), and the counts of the
 // row are written.
-__global__ __launch_bounds__(256) void k_lists_count(int64_t nbox, const double* __restrict__ geom,
+__global__ __launch_bounds__(64) void k_lists_count(int64_t nbox, const double* __restrict__ geom,
                                                      const double4* __restrict__ cr,
                                                      const int64_t* __restrict__ ps_off,
                                                      const int32_t* __restrict__ ps_idx, double theta,
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_lists_count(int64_t nbox, const double*
 
 // Fill pass: the candidates again, in the same order, sorted into the rows
 // by the count pass's mask words (no geometry, no test).
-__global__ __launch_bounds__(256) void k_lists_fill(int64_t nbox, const int64_t* __restrict__ ps_off,
+__global__ __launch_bounds__(64) void k_lists_fill(int64_t nbox, const int64_t* __restrict__ ps_off,
                                                     const int32_t* __restrict__ ps_idx,
                                                     const int64_t* __restrict__ wofs,
                                                     const int32_t* __restrict__ words,
@@ -314,8 +314,8 @@ void lists_build(Tree& t, hipStream_t s) {
     // entries) + 8 npar, known on the host without a read-back
     const int64_t nwords = P.s_nnz + 8 * npar;
     uint64_t* mask = (uint64_t*)dalloc(std::max<int64_t>(1, nwords) * sizeof(uint64_t), s);
-    const unsigned grid = (unsigned)(8 * (((nb + 3) / 4 + 7) / 8));
-    k_lists_count<<<grid, 256, 0, s>>>(nb, V.geom, cr, P.s_off, P.s_idx, t.theta, wofs, words, mask, ns, nw);
+    const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
+    k_lists_count<<<grid, 64, 0, s>>>(nb, V.geom, cr, P.s_off, P.s_idx, t.theta, wofs, words, mask, ns, nw);
     HIPCHECK(hipGetLastError());
     V.s_off = (int64_t*)dalloc((nb + 1) * sizeof(int64_t), s);
     V.w_off = (int64_t*)dalloc((nb + 1) * sizeof(int64_t), s);
@@ -329,7 +329,7 @@ void lists_build(Tree& t, hipStream_t s) {
     m2l += V.w_nnz;
     V.s_idx = (int32_t*)dalloc(std::max<int64_t>(1, V.s_nnz) * sizeof(int32_t), s);
     V.w_idx = (int32_t*)dalloc(std::max<int64_t>(1, V.w_nnz) * sizeof(int32_t), s);
-    k_lists_fill<<<grid, 256, 0, s>>>(nb, P.s_off, P.s_idx, wofs, words, mask, V.s_off, V.s_idx, V.w_off,
+    k_lists_fill<<<grid, 64, 0, s>>>(nb, P.s_off, P.s_idx, wofs, words, mask, V.s_off, V.s_idx, V.w_off,
                                       V.w_idx);
     HIPCHECK(hipGetLastError());
     dfree(mask, s);
