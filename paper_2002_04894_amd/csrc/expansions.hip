@@ -606,8 +606,14 @@ __device__ __forceinline__ int level_of(const LevelView& lv, int64_t gid) {
 }
 
 // ---- M2M: parents of level l-1 from their 8 children on level l ----
+// The three coefficient vectors of a translation (X, T, acc) live in dynamic
+// LDS sized for the order, tb.nt doubles each (4 KB at p 12 instead of 10.3 KB
+// for the highest order), so more workgroups fit on a CU.
 __global__ __launch_bounds__(64) void k_m2m(LevelView lv, int l, XT tb, double* __restrict__ Mx) {
-  __shared__ double X[kNtMax], T[kNtMax], acc[kNtMax];
+  extern __shared__ double xs[];
+  double* X = xs;
+  double* T = xs + tb.nt;
+  double* acc = xs + 2 * tb.nt;
   __shared__ XScratch sc;
   const int lane = threadIdx.x;
   const int nt = tb.nt;
@@ -626,10 +632,17 @@ __global__ __launch_bounds__(64) void k_m2m(LevelView lv, int l, XT tb, double* 
 }
 
 // ---- L2L: children of level l receive their parent's local expansion ----
-__global__ __launch_bounds__(64) void k_l2l(LevelView lv, int l, XT tb, double* __restrict__ Lx) {
-  __shared__ double X[kNtMax], T[kNtMax], acc[kNtMax];
+// One workgroup per child; the workgroups are dealt to the eight XCDs in
+// turn, so child (b mod 8) ceil(nbox / 8) + floor(b / 8) goes to block b:
+// siblings, which read the same parent expansion, share an XCD's L2.
+__global__ __launch_bounds__(64) void k_l2l(LevelView lv, int l, int64_t nbox, XT tb, double* __restrict__ Lx) {
+  extern __shared__ double xs[];
+  double* X = xs;
+  double* T = xs + tb.nt;
+  double* acc = xs + 2 * tb.nt;
   __shared__ XScratch sc;
-  const int64_t ch = blockIdx.x;
+  const int64_t ch = (int64_t)(blockIdx.x % 8) * ((nbox + 7) / 8) + blockIdx.x / 8;
+  if (ch >= nbox) return;
   const int64_t par = ch >> 3;
   const double* gc = lv.geom[l] + ch * 10;
   const double* gp = lv.geom[l - 1] + par * 10;
@@ -819,7 +832,8 @@ void launch_p2m(const Tree& t, const Tables& tb, const double* qt, double* Mx, h
   HIPCHECK(hipGetLastError());
 }
 void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s) {
-  k_m2m<<<(unsigned)t.lev[l - 1].nbox, 64, 0, s>>>(t.view(), l, make_xt(tb), Mx);
+  const size_t lds = 3 * (size_t)nterms(tb.p) * sizeof(double);
+  k_m2m<<<(unsigned)t.lev[l - 1].nbox, 64, lds, s>>>(t.view(), l, make_xt(tb), Mx);
   HIPCHECK(hipGetLastError());
 }
 bool launch_m2l_mfma(const Tree& t, const Tables& tb, const double* Mx, double* Lx, hipStream_t s);
@@ -837,7 +851,9 @@ void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, i
   fail(FMM_EUNSUPPORTED, "no M2L kernel for order " + std::to_string(tb.p));
 }
 void launch_l2l(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s) {
-  k_l2l<<<(unsigned)t.lev[l].nbox, 64, 0, s>>>(t.view(), l, make_xt(tb), Lx);
+  const int64_t nbox = t.lev[l].nbox;
+  const size_t lds = 3 * (size_t)nterms(tb.p) * sizeof(double);
+  k_l2l<<<(unsigned)(8 * ((nbox + 7) / 8)), 64, lds, s>>>(t.view(), l, nbox, make_xt(tb), Lx);
   HIPCHECK(hipGetLastError());
 }
 void launch_l2p(const Tree& t, const Tables& tb, const double* Lx, const int32_t* start, const double* px,
