@@ -779,41 +779,51 @@ __global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const int32_t* 
         const double nzr = a * (x * mzr - y * mzi), nzi = a * (x * mzi + y * mzr);
         mr = nr; mi = ni; mxr = nxr; mxi = nxi; myr = nyr; myi = nyi; mzr = nzr; mzi = nzi;
       }
-      double g1[8] = {mr, mi, mxr, mxi, myr, myi, mzr, mzi};
-      double g2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int n = m; n <= p; ++n) {
-        double gn[8];
-        if (n == m) {
-          for (int u = 0; u < 8; ++u) gn[u] = g1[u];
-        } else if (n == m + 1) {
-          const double bb = bm[m];
-          gn[0] = bb * z * mr; gn[1] = bb * z * mi;
-          gn[2] = bb * z * mxr; gn[3] = bb * z * mxi;
-          gn[4] = bb * z * myr; gn[5] = bb * z * myi;
-          gn[6] = bb * (mr + z * mzr); gn[7] = bb * (mi + z * mzi);
-        } else {
-          const double a1 = c1[n * P1 + m], a2 = c2[n * P1 + m];
-          gn[0] = a1 * z * g1[0] - a2 * r2 * g2[0];
-          gn[1] = a1 * z * g1[1] - a2 * r2 * g2[1];
-          gn[2] = a1 * z * g1[2] - a2 * (r2 * g2[2] + 2.0 * x * g2[0]);
-          gn[3] = a1 * z * g1[3] - a2 * (r2 * g2[3] + 2.0 * x * g2[1]);
-          gn[4] = a1 * z * g1[4] - a2 * (r2 * g2[4] + 2.0 * y * g2[0]);
-          gn[5] = a1 * z * g1[5] - a2 * (r2 * g2[5] + 2.0 * y * g2[1]);
-          gn[6] = a1 * (g1[0] + z * g1[6]) - a2 * (r2 * g2[6] + 2.0 * z * g2[0]);
-          gn[7] = a1 * (g1[1] + z * g1[7]) - a2 * (r2 * g2[7] + 2.0 * z * g2[1]);
-        }
-        if (n > m) {
-          for (int u = 0; u < 8; ++u) {
-            g2[u] = g1[u];
-            g1[u] = gn[u];
-          }
-        }
-        const double lc = Lc[pos[cidx(n, m, 0)]] * (m == 0 ? 1.0 : s2);
+      // degree n = m, then n = m + 1, then the three-term recurrence, two
+      // degrees per pass so that the two history arrays alternate roles
+      // instead of being copied: ga holds G_{n-2} and receives G_n, gb holds
+      // G_{n-1}
+      const double msc = m == 0 ? 1.0 : s2;
+      auto add = [&](const double* g, int n) __attribute__((always_inline)) {
+        const double lc = Lc[pos[cidx(n, m, 0)]] * msc;
         const double ls = m == 0 ? 0.0 : Lc[pos[cidx(n, m, 1)]] * s2;
-        f += lc * gn[0] + ls * gn[1];
-        fx += lc * gn[2] + ls * gn[3];
-        fy += lc * gn[4] + ls * gn[5];
-        fz += lc * gn[6] + ls * gn[7];
+        f += lc * g[0] + ls * g[1];
+        fx += lc * g[2] + ls * g[3];
+        fy += lc * g[4] + ls * g[5];
+        fz += lc * g[6] + ls * g[7];
+      };
+      // G_n from G_{n-1} (gb) and G_{n-2} (ga, overwritten; its components 0
+      // and 1 are read by the gradient terms, so they are replaced last)
+      auto rec = [&](double* ga, const double* gb, int n) __attribute__((always_inline)) {
+        const double a1 = c1[n * P1 + m], a2 = c2[n * P1 + m];
+        const double g0 = ga[0], g1v = ga[1];
+        ga[2] = a1 * z * gb[2] - a2 * (r2 * ga[2] + 2.0 * x * g0);
+        ga[3] = a1 * z * gb[3] - a2 * (r2 * ga[3] + 2.0 * x * g1v);
+        ga[4] = a1 * z * gb[4] - a2 * (r2 * ga[4] + 2.0 * y * g0);
+        ga[5] = a1 * z * gb[5] - a2 * (r2 * ga[5] + 2.0 * y * g1v);
+        ga[6] = a1 * (gb[0] + z * gb[6]) - a2 * (r2 * ga[6] + 2.0 * z * g0);
+        ga[7] = a1 * (gb[1] + z * gb[7]) - a2 * (r2 * ga[7] + 2.0 * z * g1v);
+        ga[0] = a1 * z * gb[0] - a2 * r2 * g0;
+        ga[1] = a1 * z * gb[1] - a2 * r2 * g1v;
+      };
+      double gA[8] = {mr, mi, mxr, mxi, myr, myi, mzr, mzi};  // G_m^m
+      add(gA, m);
+      if (m < p) {
+        const double bb = bm[m];
+        double gB[8] = {bb * z * mr,  bb * z * mi,  bb * z * mxr,         bb * z * mxi,
+                        bb * z * myr, bb * z * myi, bb * (mr + z * mzr), bb * (mi + z * mzi)};  // G_{m+1}^m
+        add(gB, m + 1);
+        int n = m + 2;
+        for (; n + 1 <= p; n += 2) {
+          rec(gA, gB, n);
+          add(gA, n);
+          rec(gB, gA, n + 1);
+          add(gB, n + 1);
+        }
+        if (n <= p) {
+          rec(gA, gB, n);
+          add(gA, n);
+        }
       }
     }
     fphi[t] = f;
