@@ -425,8 +425,6 @@ const Tables& tables_for(int p, hipStream_t s) {
 // ----------------------------------------------------------------------------
 namespace {
 
-constexpr int kNtMax = (kMaxOrder + 1) * (kMaxOrder + 1);
-
 struct XT {
   int p;
   int nt;
@@ -657,25 +655,22 @@ __global__ __launch_bounds__(64) void k_l2l(LevelView lv, int l, int64_t nbox, X
 // ---- P2M: one 64-lane workgroup per leaf, lanes over points ----
 // For each order m every lane puts its point's terms of degrees m..p (cosine
 // and sine parts: the columns) into one LDS row; then each column is summed
-// over the 64 rows in a fixed order, by one lane (more than 32 columns) or by
-// two lanes of 32 rows each whose halves are then added.  The row stride
-// p2m_stride(p) is odd, so the row writes and the column reads are free of
-// bank conflicts.
+// over the 64 rows in a fixed order by g lanes (g the largest power of two
+// with g * columns <= 64), each adding every g-th row, and g - 1 exchanges
+// add their partial sums.  The row stride p2m_stride(p) is odd, so the row
+// writes and the column reads are free of bank conflicts.
 __host__ __device__ constexpr int p2m_stride(int p) { return 2 * (p + 1) + 1; }
 
 __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* __restrict__ px,
                                             const double* __restrict__ py, const double* __restrict__ pz,
                                             const double* __restrict__ qt, double* __restrict__ Mx) {
-  __shared__ double acc[kNtMax];
-  extern __shared__ double rows[];  // 64 x p2m_stride(p)
+  extern __shared__ double rows[];  // 64 x p2m_stride(p), then the sums (tb.nt)
   const int lane = threadIdx.x;
   const int L = lv.L, p = tb.p, P1 = p + 1, nt = tb.nt;
   const int64_t b = blockIdx.x;
   const double* g = lv.geom[L] + b * 10;
   const double cx = g[6], cy = g[7], cz = g[8];
   const int s0 = lv.start[L][b], s1 = lv.start[L][b + 1];
-  for (int k = lane; k < nt; k += 64) acc[k] = 0.0;
-  __syncthreads();
   const double* am = tb.rc;
   const double* bm = tb.rc + P1;
   const double* c1 = tb.rc + 2 * P1;
@@ -683,6 +678,9 @@ __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* _
   const double s2 = 1.4142135623730951;
   const int SP = p2m_stride(p);
   double* row = rows + lane * SP;
+  double* acc = rows + 64 * SP;
+  for (int k = lane; k < nt; k += 64) acc[k] = 0.0;
+  __syncthreads();
   for (int c0 = s0; c0 < s1; c0 += 64) {
     const int t = c0 + lane;
     const bool valid = t < s1;
@@ -699,40 +697,46 @@ __global__ __launch_bounds__(64) void k_p2m(LevelView lv, XT tb, const double* _
         mr = nr;
         mi = ni;
       }
-      double g2r = 0, g2i = 0, g1r = mr, g1i = mi;  // G_{n-2}, G_{n-1}
-      for (int n = m; n <= p; ++n) {
-        double gr, gi;
-        if (n == m) {
-          gr = mr;
-          gi = mi;
-        } else if (n == m + 1) {
-          gr = bm[m] * z * mr;
-          gi = bm[m] * z * mi;
-        } else {
-          gr = c1[n * P1 + m] * z * g1r - c2[n * P1 + m] * r2 * g2r;
-          gi = c1[n * P1 + m] * z * g1i - c2[n * P1 + m] * r2 * g2i;
+      // degrees m and m + 1, then the three-term recurrence two degrees per
+      // pass: (ar, ai) holds G_{n-2} and receives G_n, (br, bi) holds G_{n-1}
+      const double cq = (m == 0 ? 1.0 : s2) * q, sq = s2 * q;
+      double ar = mr, ai = mi;
+      row[0] = cq * ar;
+      row[1] = sq * ai;
+      if (m < p) {
+        double br = bm[m] * z * mr, bi = bm[m] * z * mi;
+        row[2] = cq * br;
+        row[3] = sq * bi;
+        int n = m + 2;
+        for (; n + 1 <= p; n += 2) {
+          ar = c1[n * P1 + m] * z * br - c2[n * P1 + m] * r2 * ar;
+          ai = c1[n * P1 + m] * z * bi - c2[n * P1 + m] * r2 * ai;
+          row[2 * (n - m)] = cq * ar;
+          row[2 * (n - m) + 1] = sq * ai;
+          br = c1[(n + 1) * P1 + m] * z * ar - c2[(n + 1) * P1 + m] * r2 * br;
+          bi = c1[(n + 1) * P1 + m] * z * ai - c2[(n + 1) * P1 + m] * r2 * bi;
+          row[2 * (n + 1 - m)] = cq * br;
+          row[2 * (n + 1 - m) + 1] = sq * bi;
         }
-        if (n > m) {
-          g2r = g1r;
-          g2i = g1i;
-          g1r = gr;
-          g1i = gi;
+        if (n <= p) {
+          ar = c1[n * P1 + m] * z * br - c2[n * P1 + m] * r2 * ar;
+          ai = c1[n * P1 + m] * z * bi - c2[n * P1 + m] * r2 * ai;
+          row[2 * (n - m)] = cq * ar;
+          row[2 * (n - m) + 1] = sq * ai;
         }
-        row[2 * (n - m)] = (m == 0 ? 1.0 : s2) * q * gr;
-        row[2 * (n - m) + 1] = s2 * q * gi;
       }
       __syncthreads();
-      // column col = 2 (n - m) + part of every row
+      // column col = 2 (n - m) + part of every row; g lanes per column
       const int ncol = 2 * (P1 - m);
-      const bool two = ncol <= 32;
-      const int col = two ? lane >> 1 : lane;
-      const int r0 = two ? 32 * (lane & 1) : 0, nr = two ? 32 : 64;
+      int g = 1;
+      while (2 * g * ncol <= 64) g *= 2;
+      const int col = lane / g, sub = lane % g;
       double v = 0.0;
       if (col < ncol)
-        for (int r = r0; r < r0 + nr; ++r) v += rows[r * SP + col];
-      if (two) v += __shfl_xor(v, 1);
+        for (int r = sub; r < 64; r += g) v += rows[r * SP + col];
+      for (int d = 1; d < g; d <<= 1) v += __shfl_xor(v, d);
       const int n = m + (col >> 1), part = col & 1;
-      if (col < ncol && (!two || (lane & 1) == 0) && (m > 0 || part == 0)) acc[cidx(n, m, part)] += v;
+      if (col < ncol && sub == 0 && (m > 0 || part == 0)) acc[cidx(n, m, part)] += v;
       __syncthreads();
     }
   }
@@ -837,7 +841,7 @@ __global__ __launch_bounds__(64) void k_l2p(LevelView lv, XT tb, const int32_t* 
 
 // launch helpers used by evaluate() (p2p.hip)
 void launch_p2m(const Tree& t, const Tables& tb, const double* qt, double* Mx, hipStream_t s) {
-  const size_t lds = (size_t)64 * p2m_stride(tb.p) * sizeof(double);
+  const size_t lds = ((size_t)64 * p2m_stride(tb.p) + nterms(tb.p)) * sizeof(double);
   k_p2m<<<(unsigned)t.lev[t.L].nbox, 64, lds, s>>>(t.view(), make_xt(tb), t.px, t.py, t.pz, qt, Mx);
   HIPCHECK(hipGetLastError());
 }
