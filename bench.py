@@ -57,7 +57,7 @@ M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", 
         "write_kib": 479565723.84375,
     },
     ("k_m2l_quad<12>", 1 << 27, 0.6): {
-        "sources_sha256": "e02200a47f9a5f2a0feb0d3dbdf98e56e552908bea1938538c7008547c9eb57f",
+        "sources_sha256": "57efc6cadba8790ce7f948d1f2e8878084334922801114bcd22bd3422f9c4f5c",
         "fetch_kib": 10546731641.875,
         "write_kib": 17000206.6875,
     },

@@ -330,9 +330,13 @@ std::vector<float> lane_tables(const HostTables& h, int p) {
   return out;
 }
 
-// The operands of the binary64 per-quad M2L kernel (lane_ops.h): J and, where
-// it fits, J^T as 4x4 parts in instruction order, then the z-translation core.
-std::vector<double> quad_tables(const HostTables& h, int p) {
+// The operands of the binary64 per-quad kernels (lane_ops.h): J and, where it
+// fits, J^T as 4x4 parts in instruction order, then the z-translation core
+// Z[m][d][n] (output degree d, input degree n) of the given kind: for M2L
+// A[m][d][n]; for M2M B[m][d][n] (n <= d) and for L2L B[m][n][d] (n >= d),
+// the powers of the distance applied apart.
+enum QuadKind { kQuadM2L = 0, kQuadM2M = 1, kQuadL2L = 2 };
+std::vector<double> quad_tables(const HostTables& h, int p, int kind) {
   using namespace lops;
   std::vector<double> out((size_t)qtable_doubles(p), 0.0);
   const int ntab = qtable_has_jt(p) ? 2 : 1;
@@ -357,7 +361,16 @@ std::vector<double> quad_tables(const HostTables& h, int p) {
   const size_t P1 = (size_t)p + 1;
   for (int m = 0; m <= p; ++m)
     for (int d = m; d <= p; ++d)
-      for (int n = m; n <= p; ++n) Z[((size_t)m * P1 + d) * P1 + n] = h.A[((size_t)m * P1 + d) * P1 + n];
+      for (int n = m; n <= p; ++n) {
+        double v;
+        if (kind == kQuadM2L)
+          v = h.A[((size_t)m * P1 + d) * P1 + n];
+        else if (kind == kQuadM2M)
+          v = n <= d ? h.B[((size_t)m * P1 + d) * P1 + n] : 0.0;
+        else
+          v = n >= d ? h.B[((size_t)m * P1 + n) * P1 + d] : 0.0;
+        Z[((size_t)m * P1 + d) * P1 + n] = v;
+      }
   return out;
 }
 
@@ -409,7 +422,11 @@ const Tables& tables_for(int p, hipStream_t s) {
   t.pos = upload(h.pos, s);
   t.ipos = upload(h.ipos, s);
   t.tiled = h.tiled;
-  t.quad = upload(quad_tables(h, p), s);
+  t.quad = upload(quad_tables(h, p, kQuadM2L), s);
+  if (p <= kQuadXlateMaxP) {
+    t.quad_m2m = upload(quad_tables(h, p, kQuadM2M), s);
+    t.quad_l2l = upload(quad_tables(h, p, kQuadL2L), s);
+  }
   if (h.tiled) {
     t.mtab = upload(h.mtab, s);
     t.mtab32 = upload(h.mtab32, s);
@@ -845,7 +862,13 @@ void launch_p2m(const Tree& t, const Tables& tb, const double* qt, double* Mx, h
   k_p2m<<<(unsigned)t.lev[t.L].nbox, 64, lds, s>>>(t.view(), make_xt(tb), t.px, t.py, t.pz, qt, Mx);
   HIPCHECK(hipGetLastError());
 }
+bool launch_m2m_quad64(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s);
+bool launch_l2l_quad64(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s);
+
+// M2M and L2L four lanes per translation on the matrix cores up to order
+// kQuadXlateMaxP, the generic translation above
 void launch_m2m(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s) {
+  if (launch_m2m_quad64(t, l, tb, Mx, s)) return;
   const size_t lds = 3 * (size_t)nterms(tb.p) * sizeof(double);
   k_m2m<<<(unsigned)t.lev[l - 1].nbox, 64, lds, s>>>(t.view(), l, make_xt(tb), Mx);
   HIPCHECK(hipGetLastError());
@@ -865,6 +888,7 @@ void launch_m2l(const Tree& t, const Tables& tb, const double* Mx, double* Lx, i
   fail(FMM_EUNSUPPORTED, "no M2L kernel for order " + std::to_string(tb.p));
 }
 void launch_l2l(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s) {
+  if (launch_l2l_quad64(t, l, tb, Lx, s)) return;
   const int64_t nbox = t.lev[l].nbox;
   const size_t lds = 3 * (size_t)nterms(tb.p) * sizeof(double);
   k_l2l<<<(unsigned)(8 * ((nbox + 7) / 8)), 64, lds, s>>>(t.view(), l, nbox, make_xt(tb), Lx);

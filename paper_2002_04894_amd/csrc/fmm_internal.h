@@ -14,6 +14,9 @@ namespace fmm {
 constexpr int kWave = 64;
 constexpr int kMaxLevels = FMM_MAX_LEVELS;
 constexpr int kMaxOrder = FMM_MAX_ORDER;
+// M2M and L2L run four lanes per translation on the matrix cores up to this
+// order (two waves per SIMD), the generic binary64 translation above
+constexpr int kQuadXlateMaxP = 13;
 
 inline int nterms(int p) { return (p + 1) * (p + 1); }
 
@@ -153,8 +156,12 @@ struct Tables {
   // kernel's 4x4x1 matrix instructions (lane_ops.h), binary32
   float* lane = nullptr;
   // J, J^T (where it fits in LDS) and the z-translation core for the
-  // binary64 per-quad M2L kernel (lane_ops.h)
+  // binary64 per-quad M2L kernel (lane_ops.h), and the same with the M2M and
+  // L2L cores for the per-quad translation kernel (orders up to
+  // kQuadXlateMaxP)
   double* quad = nullptr;
+  double* quad_m2m = nullptr;
+  double* quad_l2l = nullptr;
   bool tiled = false;
 };
 const Tables& tables_for(int p, hipStream_t s);

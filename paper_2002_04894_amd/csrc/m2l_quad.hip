@@ -236,6 +236,31 @@ struct QuadCfg {
   static_assert(kLds * 8 <= 160 * 1024, "the tables must fit in LDS");
 };
 
+// One step of the translation, kept apart from its neighbours by the
+// scheduler (bounds the registers in flight)
+#define FMM_QSTEP(x) \
+  x;                 \
+  __builtin_amdgcn_sched_barrier(0)
+
+// A halving exchange over lanes at distance DIST of a wave whose lane holds
+// N_SRC values SRC: lanes with that lane bit clear keep the lower N_DST values
+// and receive their partner's, the others the upper ones (zero-padded), and
+// each keeps the sums in DST.  Uses `lane`.
+#define FMM_QHALVE(SRC, N_SRC, DST, N_DST, DIST)                         \
+  double DST[N_DST];                                                    \
+  {                                                                     \
+    const bool up = (lane & (DIST)) != 0;                               \
+    _Pragma("unroll") for (int i = 0; i < (N_DST); ++i) {               \
+      const int ih = (N_DST) + i < (N_SRC) ? (N_DST) + i : (N_SRC) - 1; \
+      const double lo = SRC[i];                                         \
+      const double hi = (N_DST) + i < (N_SRC) ? SRC[ih] : 0.0;          \
+      const double send = up ? lo : hi;                                 \
+      const double keep = up ? hi : lo;                                 \
+      DST[i] = keep + __shfl_xor(send, (DIST));                         \
+      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);              \
+    }                                                                   \
+  }
+
 template <int P>
 __global__ __launch_bounds__(QuadCfg<P>::kThreads)
 __attribute__((amdgpu_waves_per_eu(QuadCfg<P>::kWaves, QuadCfg<P>::kWaves))) void
@@ -294,9 +319,6 @@ k_m2l_quad(LevelView lv, const double* __restrict__ qtab, const int* __restrict_
 #pragma unroll
       for (int r = 0; r < NQ; ++r) X[r] = src[4 * r];
 
-#define FMM_QSTEP(x) \
-  x;                 \
-  __builtin_amdgcn_sched_barrier(0)
       FMM_QSTEP(qrotz<P>(X, cb, sb, -1.0, k));
       FMM_QSTEP((qjapply<P, !HJT>(X, HJT ? tabs + NJ : tabs, HJT ? tl : tlt)));
       FMM_QSTEP(qrotz<P>(X, ca, sa, -1.0, k));
@@ -306,30 +328,12 @@ k_m2l_quad(LevelView lv, const double* __restrict__ qtab, const int* __restrict_
       FMM_QSTEP(qrotz<P>(X, ca, sa, 1.0, k));
       FMM_QSTEP((qjapply<P, false>(X, tabs, tl)));
       FMM_QSTEP(qrotz<P>(X, cb, sb, 1.0, k));
-#undef FMM_QSTEP
 
-      // sum over the 16 pairs (lane bits 0..3): four halving exchanges; at
-      // the exchange with lane distance dist the lanes with that bit clear
-      // keep the lower half
-#define FMM_QHALVE(SRC, N_SRC, DST, N_DST, DIST)                         \
-  double DST[N_DST];                                                    \
-  {                                                                     \
-    const bool up = (lane & (DIST)) != 0;                               \
-    _Pragma("unroll") for (int i = 0; i < (N_DST); ++i) {               \
-      const int ih = (N_DST) + i < (N_SRC) ? (N_DST) + i : (N_SRC) - 1; \
-      const double lo = SRC[i];                                         \
-      const double hi = (N_DST) + i < (N_SRC) ? SRC[ih] : 0.0;          \
-      const double send = up ? lo : hi;                                 \
-      const double keep = up ? hi : lo;                                 \
-      DST[i] = keep + __shfl_xor(send, (DIST));                         \
-      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);              \
-    }                                                                   \
-  }
+      // sum over the 16 pairs (lane bits 0..3): four halving exchanges
       FMM_QHALVE(X, NQ, h1, qlvl(NQ, 1), 8)
       FMM_QHALVE(h1, qlvl(NQ, 1), h2, qlvl(NQ, 2), 4)
       FMM_QHALVE(h2, qlvl(NQ, 2), h3, qlvl(NQ, 3), 2)
       FMM_QHALVE(h3, qlvl(NQ, 3), h4, qlvl(NQ, 4), 1)
-#undef FMM_QHALVE
 #pragma unroll
       for (int i = 0; i < NF; ++i) acc[i] += h4[i];
     }
@@ -425,6 +429,162 @@ void launch_one_quad(const Tree& t, const Tables& tb, const double* Mx, double* 
   dfree(Mq, s);
 }
 
+// ---- M2M and L2L, four lanes per translation (Algorithm 1 M2M, Algorithm 3
+// L2L; orders up to kQuadXlateMaxP) ----
+// The rotations and quarter turns of the M2L kernel with the M2M or L2L core
+// along z; the distance powers are applied apart (M2M: input degree n times
+// rho^-n, output degree d times rho^d; L2L the reverse), in binary64 without
+// radius scaling.  A wave takes 16 children of level l, the children of two
+// parents: M2M sums each parent's eight translated children by three halving
+// exchanges and writes the parent (and zeroes its storage's padding slots);
+// L2L adds the parent's translated expansion into each child.  The vector is
+// child centre - parent centre for both, as in the generic translation, and
+// a pair at distance zero is the identity (its input is added back).
+template <int P, bool L2L>
+__global__ __launch_bounds__(QuadCfg<P>::kThreads)
+__attribute__((amdgpu_waves_per_eu(QuadCfg<P>::kWaves, QuadCfg<P>::kWaves))) void
+k_xlate_quad(LevelView lv, int l, const double* __restrict__ qtab, const int* __restrict__ pos,
+             const int* __restrict__ ipos, int S, double* __restrict__ E, int64_t ngroup) {
+  constexpr int NQ = lops::nq(P);
+  constexpr int NJ = QuadCfg<P>::kJ;
+  constexpr int NL = QuadCfg<P>::kLds;
+  constexpr int NF = qlvl(NQ, 3);  // values a lane holds after the M2M exchanges
+  static_assert(lops::qtable_has_jt(P), "orders whose table holds J^T");
+  __shared__ double tabs[NL];
+  __shared__ int spos[NQ * 4];  // storage position of (register, phase); -1: zero slot
+  for (int i = threadIdx.x; i < NL; i += blockDim.x) tabs[i] = qtab[i];
+  for (int t = threadIdx.x; t < NQ * 4; t += blockDim.x) {
+    const int R = t >> 2, ph = t & 3;
+    const int d = qdeg(R);
+    const int x = R - lops::qbase(d, 0) >= lops::qreg(d) ? 1 : 0;
+    const int mi = lops::qmember(d, x, 4 * (R - lops::qbase(d, x)) + ph);
+    spos[t] = mi >= 0 ? pos[d * d + mi] : -1;
+  }
+  __syncthreads();
+  const double* Az = tabs + 2 * NJ;
+  const int lane = threadIdx.x & 63;
+  const int k = lane >> 4, q = lane & 15;
+  const int tl = 4 * k + (lane & 3);
+  const double* gch = lv.geom[l];
+  const double* gpa = lv.geom[l - 1];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t cg = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); cg < ngroup; cg += nw) {
+    const int64_t ch = 16 * cg + q, par = ch >> 3;
+    const double dx = gch[ch * 10 + 6] - gpa[par * 10 + 6];
+    const double dy = gch[ch * 10 + 7] - gpa[par * 10 + 7];
+    const double dz = gch[ch * 10 + 8] - gpa[par * 10 + 8];
+    const double rxy2 = dx * dx + dy * dy;
+    const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
+    const bool zero = !(rho > 0.0);
+    const double irho = zero ? 0.0 : 1.0 / rho;
+    const double ca = zero ? 1.0 : dz * irho, sa = zero ? 0.0 : rxy * irho;
+    const double cb = rxy > 0.0 ? dx / rxy : 1.0, sb = rxy > 0.0 ? dy / rxy : 0.0;
+    // a pair at distance zero translates to zero here; its identity is added below
+    const double in_base = zero ? 0.0 : (L2L ? rho : irho);
+    const double out_base = zero ? 0.0 : (L2L ? irho : rho);
+    const double out_mult = zero ? 0.0 : 1.0;
+    const double* src = E + (size_t)(L2L ? lv.gofs[l - 1] + par : lv.gofs[l] + ch) * S;
+
+    double X[NQ];
+    qfor<0, NQ>([&](auto rI) __attribute__((always_inline)) {
+      const int sp = spos[4 * decltype(rI)::value + k];
+      X[decltype(rI)::value] = sp >= 0 ? src[sp] : 0.0;
+    });
+    FMM_QSTEP(qrotz<P>(X, cb, sb, -1.0, k));
+    FMM_QSTEP((qjapply<P, false>(X, tabs + NJ, tl)));
+    FMM_QSTEP(qrotz<P>(X, ca, sa, -1.0, k));
+    FMM_QSTEP((qjapply<P, false>(X, tabs, tl)));
+    FMM_QSTEP(qztrans<P>(X, Az, k, in_base, out_base, out_mult));
+    FMM_QSTEP((qjapply<P, false>(X, tabs + NJ, tl)));
+    FMM_QSTEP(qrotz<P>(X, ca, sa, 1.0, k));
+    FMM_QSTEP((qjapply<P, false>(X, tabs, tl)));
+    FMM_QSTEP(qrotz<P>(X, cb, sb, 1.0, k));
+    if (__ballot(zero)) {
+      qfor<0, NQ>([&](auto rI) __attribute__((always_inline)) {
+        const int sp = spos[4 * decltype(rI)::value + k];
+        if (zero && sp >= 0) X[decltype(rI)::value] += src[sp];
+      });
+    }
+
+    if constexpr (L2L) {
+      double* dst = E + (size_t)(lv.gofs[l] + ch) * S;
+      qfor<0, NQ>([&](auto rI) __attribute__((always_inline)) {
+        const int sp = spos[4 * decltype(rI)::value + k];
+        if (sp >= 0) dst[sp] += X[decltype(rI)::value];
+      });
+    } else {
+      // sum over the eight children of each parent (lane bits 0..2)
+      FMM_QHALVE(X, NQ, h1, qlvl(NQ, 1), 4)
+      FMM_QHALVE(h1, qlvl(NQ, 1), h2, qlvl(NQ, 2), 2)
+      FMM_QHALVE(h2, qlvl(NQ, 2), h3, qlvl(NQ, 3), 1)
+      // lane's values: registers base + i of phase k of parent 2 cg + (q >> 3)
+      int base = 0, len = NQ;
+#pragma unroll
+      for (int sidx = 1; sidx <= 3; ++sidx) {
+        const int half = qlvl(NQ, sidx);
+        if (lane & (8 >> sidx)) {
+          base += half;
+          len = len - half > 0 ? len - half : 0;
+        } else {
+          len = len < half ? len : half;
+        }
+      }
+      double* dst = E + (size_t)(lv.gofs[l - 1] + 2 * cg + (q >> 3)) * S;
+      qfor<0, NF>([&](auto iI) __attribute__((always_inline)) {
+        constexpr int i = decltype(iI)::value;
+        if (i < len) {
+          const int sp = spos[4 * (base + i) + k];
+          if (sp >= 0) dst[sp] = h3[i];
+        }
+      });
+      double* pdst = E + (size_t)(lv.gofs[l - 1] + 2 * cg) * S;
+      for (int t = lane; t < 2 * S; t += 64)
+        if (ipos[t % S] < 0) pdst[t] = 0.0;
+    }
+  }
+}
+
+template <int P, bool L2L>
+void launch_one_xlate(const Tree& t, int l, const Tables& tb, double* E, hipStream_t s) {
+  const int64_t ngroup = t.lev[l].nbox / 16;
+  if (ngroup <= 0) return;
+  static const int grid_max = [] {
+    int dev = 0, ncu = 0, per = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_xlate_quad<P, L2L>, QuadCfg<P>::kThreads, 0));
+    return ncu * (per > 0 ? per : 1);
+  }();
+  const int64_t need = (ngroup + QuadCfg<P>::kThreads / 64 - 1) / (QuadCfg<P>::kThreads / 64);
+  const unsigned grid = (unsigned)(need < grid_max ? need : grid_max);
+  k_xlate_quad<P, L2L><<<grid, QuadCfg<P>::kThreads, 0, s>>>(t.view(), l, L2L ? tb.quad_l2l : tb.quad_m2m, tb.pos,
+                                                              tb.ipos, tb.stride, E, ngroup);
+  HIPCHECK(hipGetLastError());
+}
+
+template <bool L2L>
+bool launch_xlate(const Tree& t, int l, const Tables& tb, double* E, hipStream_t s) {
+  switch (tb.p) {
+    case 0: launch_one_xlate<0, L2L>(t, l, tb, E, s); break;
+    case 1: launch_one_xlate<1, L2L>(t, l, tb, E, s); break;
+    case 2: launch_one_xlate<2, L2L>(t, l, tb, E, s); break;
+    case 3: launch_one_xlate<3, L2L>(t, l, tb, E, s); break;
+    case 4: launch_one_xlate<4, L2L>(t, l, tb, E, s); break;
+    case 5: launch_one_xlate<5, L2L>(t, l, tb, E, s); break;
+    case 6: launch_one_xlate<6, L2L>(t, l, tb, E, s); break;
+    case 7: launch_one_xlate<7, L2L>(t, l, tb, E, s); break;
+    case 8: launch_one_xlate<8, L2L>(t, l, tb, E, s); break;
+    case 9: launch_one_xlate<9, L2L>(t, l, tb, E, s); break;
+    case 10: launch_one_xlate<10, L2L>(t, l, tb, E, s); break;
+    case 11: launch_one_xlate<11, L2L>(t, l, tb, E, s); break;
+    case 12: launch_one_xlate<12, L2L>(t, l, tb, E, s); break;
+    case 13: launch_one_xlate<13, L2L>(t, l, tb, E, s); break;
+    default: return false;
+  }
+  static_assert(kQuadXlateMaxP == 13, "the cases above cover orders 0 .. kQuadXlateMaxP");
+  return true;
+}
+
 }  // namespace
 
 // binary64 M2L with this kernel: orders up to 13 and 16..20; false for 14
@@ -454,6 +614,16 @@ bool launch_m2l_quad64(const Tree& t, const Tables& tb, const double* Mx, double
     default: return false;
   }
   return true;
+}
+
+// M2M from level l into level l - 1, or L2L from level l - 1 into level l,
+// four lanes per translation: orders up to kQuadXlateMaxP with the tables
+// made; false for the others (the generic translation then runs)
+bool launch_m2m_quad64(const Tree& t, int l, const Tables& tb, double* Mx, hipStream_t s) {
+  return tb.quad_m2m != nullptr && t.lev[l].nbox % 16 == 0 && launch_xlate<false>(t, l, tb, Mx, s);
+}
+bool launch_l2l_quad64(const Tree& t, int l, const Tables& tb, double* Lx, hipStream_t s) {
+  return tb.quad_l2l != nullptr && t.lev[l].nbox % 16 == 0 && launch_xlate<true>(t, l, tb, Lx, s);
 }
 
 }  // namespace fmm
