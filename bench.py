@@ -57,7 +57,7 @@ M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", 
         "write_kib": 479565723.84375,
     },
     ("k_m2l_quad<12>", 1 << 27, 0.6): {
-        "sources_sha256": "57efc6cadba8790ce7f948d1f2e8878084334922801114bcd22bd3422f9c4f5c",
+        "sources_sha256": "69f5905e89a2fde85cec65de8be6db93f3981163f52bc549cc3025b4e4ef327b",
         "fetch_kib": 10546731641.875,
         "write_kib": 17000206.6875,
     },

@@ -30,6 +30,9 @@
 // Padding is per 4x4 part of a block: 1.57x the algorithmic J products at
 // order 12, against 2.42x for the 16x16 tiles of m2l_mfma.hip.  Orders 16..20
 // run here too (one wave per SIMD), where the tiles stop.
+//
+// The same steps with the M2M or L2L core along z make k_xlate_quad (end of
+// the file), which runs M2M and L2L up to order 13.
 #include <type_traits>
 
 #include "fmm_internal.h"
