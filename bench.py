@@ -57,7 +57,7 @@ M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", 
         "write_kib": 479565723.84375,
     },
     ("k_m2l_quad<12>", 1 << 27, 0.6): {
-        "sources_sha256": "69f5905e89a2fde85cec65de8be6db93f3981163f52bc549cc3025b4e4ef327b",
+        "sources_sha256": "a56d5bc7db9ac48640031aa08df4b984a4d6894428e8d176ec27d4766923fac0",
         "fetch_kib": 10546731641.875,
         "write_kib": 17000206.6875,
     },

@@ -167,17 +167,23 @@ __device__ __forceinline__ void qrotz(double* X, double c1, double s1, double si
 }
 
 // the z-axis translation: the lane's orders m = 4 g + k, both blocks, with
-// the core A[m][d][n] of its own order (Az, orders above P zero)
-template <int P>
+// the core A[m][d][n] of its own order (Az, orders above P zero).  Input
+// degree n is first multiplied by in_base^n and output degree d by out_mult
+// out_base^d; with EXP also by 2^(in_exp n) and 2^(out_exp d) (ldexp: exact,
+// and saturating only where the scaled value itself leaves the range)
+template <int P, bool EXP = false>
 __device__ __forceinline__ void qztrans(double* X, const double* __restrict__ Az, int k, double in_base,
-                                        double out_base, double out_mult) {
+                                        double out_base, double out_mult, int in_exp = 0, int out_exp = 0) {
   constexpr int P1 = P + 1;
   {
     double w = 1.0;
     qfor<0, P + 1>([&](auto dI) __attribute__((always_inline)) {
       constexpr int d = decltype(dI)::value;
       qfor<0, 2 * lops::qreg(d)>([&](auto r) __attribute__((always_inline)) {
-        X[lops::qbase(d, 0) + decltype(r)::value] *= w;
+        if constexpr (EXP)
+          X[lops::qbase(d, 0) + decltype(r)::value] = ldexp(X[lops::qbase(d, 0) + decltype(r)::value] * w, in_exp * d);
+        else
+          X[lops::qbase(d, 0) + decltype(r)::value] *= w;
       });
       w *= in_base;
     });
@@ -213,7 +219,10 @@ __device__ __forceinline__ void qztrans(double* X, const double* __restrict__ Az
     qfor<0, P + 1>([&](auto dI) __attribute__((always_inline)) {
       constexpr int d = decltype(dI)::value;
       qfor<0, 2 * lops::qreg(d)>([&](auto r) __attribute__((always_inline)) {
-        X[lops::qbase(d, 0) + decltype(r)::value] *= w;
+        if constexpr (EXP)
+          X[lops::qbase(d, 0) + decltype(r)::value] = ldexp(X[lops::qbase(d, 0) + decltype(r)::value] * w, out_exp * d);
+        else
+          X[lops::qbase(d, 0) + decltype(r)::value] *= w;
       });
       w *= out_base;
     });
@@ -437,7 +446,8 @@ void launch_one_quad(const Tree& t, const Tables& tb, const double* Mx, double* 
 // The rotations and quarter turns of the M2L kernel with the M2M or L2L core
 // along z; the distance powers are applied apart (M2M: input degree n times
 // rho^-n, output degree d times rho^d; L2L the reverse), in binary64 without
-// radius scaling.  A wave takes 16 children of level l, the children of two
+// radius scaling, each power split into one of mu in [1, 2) and an exact
+// power-of-two scaling.  A wave takes 16 children of level l, the children of two
 // parents: M2M sums each parent's eight translated children by three halving
 // exchanges and writes the parent (and zeroes its storage's padding slots);
 // L2L adds the parent's translated expansion into each child.  The vector is
@@ -479,13 +489,18 @@ k_xlate_quad(LevelView lv, int l, const double* __restrict__ qtab, const int* __
     const double rxy2 = dx * dx + dy * dy;
     const double rho = sqrt(rxy2 + dz * dz), rxy = sqrt(rxy2);
     const bool zero = !(rho > 0.0);
-    const double irho = zero ? 0.0 : 1.0 / rho;
-    const double ca = zero ? 1.0 : dz * irho, sa = zero ? 0.0 : rxy * irho;
+    const double ca = zero ? 1.0 : dz / rho, sa = zero ? 0.0 : rxy / rho;
     const double cb = rxy > 0.0 ? dx / rxy : 1.0, sb = rxy > 0.0 ? dy / rxy : 0.0;
-    // a pair at distance zero translates to zero here; its identity is added below
-    const double in_base = zero ? 0.0 : (L2L ? rho : irho);
-    const double out_base = zero ? 0.0 : (L2L ? irho : rho);
+    // rho = 2^e mu with mu in [1, 2): the powers of mu stay in range and
+    // those of 2^e are exact ldexp scalings, so no partial product leaves the
+    // binary64 range unless the scaled coefficient does.  A pair at distance
+    // zero translates to zero here; its identity is added below.
+    const int e = zero ? 0 : ilogb(rho);
+    const double mu = zero ? 0.0 : ldexp(rho, -e);
+    const double in_base = zero ? 0.0 : (L2L ? mu : 1.0 / mu);
+    const double out_base = zero ? 0.0 : (L2L ? 1.0 / mu : mu);
     const double out_mult = zero ? 0.0 : 1.0;
+    const int in_exp = L2L ? e : -e, out_exp = -in_exp;
     const double* src = E + (size_t)(L2L ? lv.gofs[l - 1] + par : lv.gofs[l] + ch) * S;
 
     double X[NQ];
@@ -497,7 +512,7 @@ k_xlate_quad(LevelView lv, int l, const double* __restrict__ qtab, const int* __
     FMM_QSTEP((qjapply<P, false>(X, tabs + NJ, tl)));
     FMM_QSTEP(qrotz<P>(X, ca, sa, -1.0, k));
     FMM_QSTEP((qjapply<P, false>(X, tabs, tl)));
-    FMM_QSTEP(qztrans<P>(X, Az, k, in_base, out_base, out_mult));
+    FMM_QSTEP((qztrans<P, true>(X, Az, k, in_base, out_base, out_mult, in_exp, out_exp)));
     FMM_QSTEP((qjapply<P, false>(X, tabs + NJ, tl)));
     FMM_QSTEP(qrotz<P>(X, ca, sa, 1.0, k));
     FMM_QSTEP((qjapply<P, false>(X, tabs, tl)));

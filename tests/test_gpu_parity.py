@@ -290,6 +290,40 @@ def test_parity_binary64_orders_16_to_20(torch, F, orc, p, L):
     gt.free()
 
 
+@pytest.mark.parametrize("k", [-40, 40])
+def test_power_of_two_scale_covariance(torch, F, k):
+    """Scaling every coordinate by 2^k scales phi by 2^-k and E by 2^-2k (1/r
+    is homogeneous of degree -1).  Every step of the path is homogeneous under
+    power-of-two scaling too: the bisections and box geometry, the theta
+    test, the harmonics, the radius-scaled M2L, the M2M and L2L on the matrix
+    cores (distance powers split into a power of a mantissa in [1, 2) and an
+    exact power of two) and the near field; so the lists are equal and the
+    results agree to rounding.  Binary64 and mixed precision, orders 8 and 13,
+    a 3-level tree; a property test that holds at any size, with no oracle."""
+    x, y, z, q = make("gmix", 6_000, seed=11)
+    s = 2.0 ** k
+    t1 = gpu_tree(torch, F, x, y, z, 3, 0.5)
+    ts = gpu_tree(torch, F, x * s, y * s, z * s, 3, 0.5)
+    for l in range(4):
+        for kind in (0, 1):
+            a, b = F.fmm_tree_lists(t1, l, kind), F.fmm_tree_lists(ts, l, kind)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), f"lists level {l} kind {kind}"
+    qd = dev(torch, q)
+    for p in (8, 13):
+        for prec in (F.FMM_PREC_F64, F.FMM_PREC_MIXED):
+            say(f"[scale] 2^{k}: p={p} precision={prec}")
+            res = []
+            for tr in (t1, ts):
+                outs = [torch.empty_like(qd) for _ in range(4)]
+                F.fmm_evaluate_tree(tr, qd, p, *outs, precision=prec)
+                torch.cuda.synchronize()
+                res.append([o.cpu().numpy() for o in outs])
+            want = [res[0][0] / s] + [e / (s * s) for e in res[0][1:]]
+            assert_close(res[1], want, what=f"scale 2^{k} p={p} precision={prec}")
+    t1.free()
+    ts.free()
+
+
 @pytest.mark.parametrize("n,L", [(8192, 2), (8300, 3), (12000, 2), (16383, 2)])
 def test_parity_sizes_with_one_chunked_round(torch, F, orc, n, L):
     """8192 <= n < 16384 source points: only the first bisection round (one
