@@ -57,9 +57,9 @@ M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", 
         "write_kib": 479565723.84375,
     },
     ("k_m2l_quad<12>", 1 << 27, 0.6): {
-        "sources_sha256": "a56d5bc7db9ac48640031aa08df4b984a4d6894428e8d176ec27d4766923fac0",
-        "fetch_kib": 10546731641.875,
-        "write_kib": 17000206.6875,
+        "sources_sha256": "7506a256e0c87c880341bd40c953d8f76270fd36dfee7dc9c089359c5c6d4cc4",
+        "fetch_kib": 10978627894.625,
+        "write_kib": 20261523.8125,
     },
 }
 

@@ -26,7 +26,7 @@
 //     all degrees, which share a lane: each lane runs it for its orders on the
 //     vector units (binary64 vector and matrix peaks are equal on this part);
 //   - the 16 pair results are summed across the lanes by halving exchanges
-//     (fixed order: deterministic) and the batches in binary64.
+//     through DPP (fixed order: deterministic) and the batches in binary64.
 // Padding is per 4x4 part of a block: 1.57x the algorithmic J products at
 // order 12, against 2.42x for the 16x16 tiles of m2l_mfma.hip.  Orders 16..20
 // run here too (one wave per SIMD), where the tiles stop.
@@ -254,24 +254,37 @@ struct QuadCfg {
   x;                 \
   __builtin_amdgcn_sched_barrier(0)
 
-// A halving exchange over lanes at distance DIST of a wave whose lane holds
-// N_SRC values SRC: lanes with that lane bit clear keep the lower N_DST values
-// and receive their partner's, the others the upper ones (zero-padded), and
-// each keeps the sums in DST.  Uses `lane`.
-#define FMM_QHALVE(SRC, N_SRC, DST, N_DST, DIST)                         \
-  double DST[N_DST];                                                    \
-  {                                                                     \
-    const bool up = (lane & (DIST)) != 0;                               \
-    _Pragma("unroll") for (int i = 0; i < (N_DST); ++i) {               \
-      const int ih = (N_DST) + i < (N_SRC) ? (N_DST) + i : (N_SRC) - 1; \
-      const double lo = SRC[i];                                         \
-      const double hi = (N_DST) + i < (N_SRC) ? SRC[ih] : 0.0;          \
-      const double send = up ? lo : hi;                                 \
-      const double keep = up ? hi : lo;                                 \
-      DST[i] = keep + __shfl_xor(send, (DIST));                         \
-      if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);              \
-    }                                                                   \
+// A halving exchange over lanes at distance D (8, 4, 2 or 1: within a row of
+// 16 lanes) of a wave whose lanes hold NS values src: lanes with that lane bit
+// clear keep the lower ND values and add their partner's, the others the
+// upper ones (zero-padded).  The partner's value is a DPP read (row_ror:8,
+// quad_perm [2,3,0,1] or [1,0,3,2]; distance 4 as two shifts, row_shl:4 and
+// row_shr:4), vector work instead of LDS permutes, which the operand reads
+// already load.
+template <int CTRL>
+__device__ __forceinline__ double qdpp(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true));
+}
+template <int NS, int ND, int D>
+__device__ __forceinline__ void qhalve(const double* src, double* dst, int lane) {
+  const bool up = (lane & D) != 0;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    const double lo = src[i];
+    const double hi = ND + i < NS ? src[ND + i] : 0.0;
+    if constexpr (D == 4) {
+      const double t0 = lo + qdpp<0x104>(lo), t1 = hi + qdpp<0x114>(hi);
+      dst[i] = up ? t1 : t0;
+    } else {
+      constexpr int C = D == 8 ? 0x128 : D == 2 ? 0x4E : 0xB1;
+      const double send = up ? lo : hi, keep = up ? hi : lo;
+      dst[i] = keep + qdpp<C>(send);
+    }
+    if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
   }
+}
 
 template <int P>
 __global__ __launch_bounds__(QuadCfg<P>::kThreads)
@@ -342,10 +355,11 @@ k_m2l_quad(LevelView lv, const double* __restrict__ qtab, const int* __restrict_
       FMM_QSTEP(qrotz<P>(X, cb, sb, 1.0, k));
 
       // sum over the 16 pairs (lane bits 0..3): four halving exchanges
-      FMM_QHALVE(X, NQ, h1, qlvl(NQ, 1), 8)
-      FMM_QHALVE(h1, qlvl(NQ, 1), h2, qlvl(NQ, 2), 4)
-      FMM_QHALVE(h2, qlvl(NQ, 2), h3, qlvl(NQ, 3), 2)
-      FMM_QHALVE(h3, qlvl(NQ, 3), h4, qlvl(NQ, 4), 1)
+      double h1[qlvl(NQ, 1)], h2[qlvl(NQ, 2)], h3[qlvl(NQ, 3)], h4[qlvl(NQ, 4)];
+      qhalve<NQ, qlvl(NQ, 1), 8>(X, h1, lane);
+      qhalve<qlvl(NQ, 1), qlvl(NQ, 2), 4>(h1, h2, lane);
+      qhalve<qlvl(NQ, 2), qlvl(NQ, 3), 2>(h2, h3, lane);
+      qhalve<qlvl(NQ, 3), qlvl(NQ, 4), 1>(h3, h4, lane);
 #pragma unroll
       for (int i = 0; i < NF; ++i) acc[i] += h4[i];
     }
@@ -532,9 +546,10 @@ k_xlate_quad(LevelView lv, int l, const double* __restrict__ qtab, const int* __
       });
     } else {
       // sum over the eight children of each parent (lane bits 0..2)
-      FMM_QHALVE(X, NQ, h1, qlvl(NQ, 1), 4)
-      FMM_QHALVE(h1, qlvl(NQ, 1), h2, qlvl(NQ, 2), 2)
-      FMM_QHALVE(h2, qlvl(NQ, 2), h3, qlvl(NQ, 3), 1)
+      double h1[qlvl(NQ, 1)], h2[qlvl(NQ, 2)], h3[qlvl(NQ, 3)];
+      qhalve<NQ, qlvl(NQ, 1), 4>(X, h1, lane);
+      qhalve<qlvl(NQ, 1), qlvl(NQ, 2), 2>(h1, h2, lane);
+      qhalve<qlvl(NQ, 2), qlvl(NQ, 3), 1>(h2, h3, lane);
       // lane's values: registers base + i of phase k of parent 2 cg + (q >> 3)
       int base = 0, len = NQ;
 #pragma unroll
