@@ -201,7 +201,8 @@ HostTables make_host_tables(int p) {
     for (int j = m; j <= p; ++j)
       for (int n = m; n <= p; ++n) {
         const long double sgn = ((n + m) & 1) ? -1.0L : 1.0L;
-        h.A[((size_t)m * P1 + j) * P1 + n] = (double)(sgn * f[n + j] / sqrtl(f[n + m] * f[n - m] * f[j + m] * f[j - m]));
+        h.A[((size_t)m * P1 + j) * P1 + n] =
+            (double)(sgn * f[n + j] / sqrtl(f[n + m] * f[n - m] * f[j + m] * f[j - m]));
         if (j <= n)
           h.B[((size_t)m * P1 + n) * P1 + j] =
               (double)(sqrtl(f[n + m] * f[n - m] / (f[j + m] * f[j - m])) / f[n - j]);

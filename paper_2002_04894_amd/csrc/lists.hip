@@ -152,23 +152,48 @@ __global__ __launch_bounds__(64) void k_lists_fill(int64_t nbox, const int64_t* 
 // (bin 0 = longest), the bins scanned, then scattered.  The order within a
 // bin is not fixed; it only schedules work, every target's result is the same.
 constexpr int kOrderBins = 4096;
+// A workgroup takes kOrderChunk consecutive boxes and counts them per bin in
+// LDS, then makes one global atomic per nonzero bin: most lists of a deep
+// level can fall into one bin (the longest), where an atomic per box would
+// serialise.
+constexpr int64_t kOrderChunk = 16384;
 
-__global__ void k_order_hist(int64_t nbox, const int64_t* __restrict__ w_off,
-                             int32_t* __restrict__ hist) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbox) return;
-  const int64_t c = w_off[i + 1] - w_off[i];
-  atomicAdd(&hist[kOrderBins - 1 - (int)(c < kOrderBins - 1 ? c : kOrderBins - 1)], 1);
+__device__ __forceinline__ int order_bin(int64_t c) {
+  return kOrderBins - 1 - (int)(c < kOrderBins - 1 ? c : kOrderBins - 1);
 }
 
-__global__ void k_order_scatter(int64_t nbox, int64_t gofs, const int64_t* __restrict__ w_off,
-                                unsigned long long* __restrict__ cursor, int32_t* __restrict__ order) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbox) return;
-  const int64_t c = w_off[i + 1] - w_off[i];
-  const int b = kOrderBins - 1 - (int)(c < kOrderBins - 1 ? c : kOrderBins - 1);
-  const unsigned long long pos = atomicAdd(&cursor[b], 1ull);
-  order[pos] = (int32_t)(gofs - 1 + i);
+__global__ __launch_bounds__(256) void k_order_hist(int64_t nbox, const int64_t* __restrict__ w_off,
+                                                    int32_t* __restrict__ hist) {
+  __shared__ int32_t h[kOrderBins];
+  for (int b = threadIdx.x; b < kOrderBins; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * kOrderChunk;
+  const int64_t i1 = nbox < i0 + kOrderChunk ? nbox : i0 + kOrderChunk;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&h[order_bin(w_off[i + 1] - w_off[i])], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBins; b += blockDim.x)
+    if (h[b] != 0) atomicAdd(&hist[b], h[b]);
+}
+
+// The same chunks: the workgroup reserves its run of slots in each bin with
+// one global atomic, then hands the slots out from LDS.
+__global__ __launch_bounds__(256) void k_order_scatter(int64_t nbox, int64_t gofs, const int64_t* __restrict__ w_off,
+                                                       unsigned long long* __restrict__ cursor,
+                                                       int32_t* __restrict__ order) {
+  __shared__ unsigned long long h[kOrderBins];
+  for (int b = threadIdx.x; b < kOrderBins; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * kOrderChunk;
+  const int64_t i1 = nbox < i0 + kOrderChunk ? nbox : i0 + kOrderChunk;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&h[order_bin(w_off[i + 1] - w_off[i])], 1ull);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBins; b += blockDim.x)
+    if (h[b] != 0) h[b] = atomicAdd(&cursor[b], h[b]);
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const unsigned long long pos = atomicAdd(&h[order_bin(w_off[i + 1] - w_off[i])], 1ull);
+    order[pos] = (int32_t)(gofs - 1 + i);
+  }
 }
 
 // ---- exclusive scan: per-block scan, scan of block sums, add ----
@@ -349,14 +374,14 @@ void lists_build(Tree& t, hipStream_t s) {
     HIPCHECK(hipMemsetAsync(hist, 0, kOrderBins * sizeof(int32_t), s));
     for (int l = 1; l <= L; ++l) {
       const Level& V = t.lev[l];
-      k_order_hist<<<(unsigned)((V.nbox + 255) / 256), 256, 0, s>>>(V.nbox, V.w_off, hist);
+      k_order_hist<<<(unsigned)((V.nbox + kOrderChunk - 1) / kOrderChunk), 256, 0, s>>>(V.nbox, V.w_off, hist);
       HIPCHECK(hipGetLastError());
     }
     scan_counts(hist, cursor, kOrderBins, 0, s);
     t.m2l_order = (int32_t*)dalloc(ntarget * sizeof(int32_t), s);
     for (int l = 1; l <= L; ++l) {
       const Level& V = t.lev[l];
-      k_order_scatter<<<(unsigned)((V.nbox + 255) / 256), 256, 0, s>>>(
+      k_order_scatter<<<(unsigned)((V.nbox + kOrderChunk - 1) / kOrderChunk), 256, 0, s>>>(
           V.nbox, V.gofs, V.w_off, (unsigned long long*)cursor, t.m2l_order);
       HIPCHECK(hipGetLastError());
     }
