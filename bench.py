@@ -52,7 +52,7 @@ COPY_WRITE_SCALE = 1.0
 M2L_COUNTERS: dict = {  # (kernel, n, theta) -> {"sources_sha256", "fetch_kib", "write_kib"}
     # profiles/m2l_counters_plummer134m.md (theta 0.6, p 12): mixed precision and binary64
     ("k_m2l_lane<12>", 1 << 27, 0.6): {
-        "sources_sha256": "a4cb93d50b888a17f4ead6f5848230b3a4f963511714ec6e3a8103966f7b4705",
+        "sources_sha256": "1e390d48b53daa9cf247241abb1bb3e2ea4ac8e19a66424d12fd0d64fb5aefd5",
         "fetch_kib": 3976133030.875,
         "write_kib": 479565723.84375,
     },
