@@ -176,6 +176,28 @@ def test_parity_edge_cases(torch, F, orc, name, P, L):
     gt.free()
 
 
+@pytest.mark.parametrize("p", [6, 12])
+def test_parity_zero_distance_translations(torch, F, orc, p):
+    """A cluster of identical points beside a separated cloud: the cluster's
+    boxes have zero extent, so children share their parent's centre and M2M
+    and L2L translate by distance zero (the identity) on the matrix-core path,
+    while M2L carries those expansions to the cloud.  Checks that such pairs
+    and weak pairs exist, then the whole result against the oracle."""
+    P = np.r_[np.full((256, 3), 0.25), np.random.default_rng(8).random((768, 3)) + 1.5]
+    x, y, z = (np.ascontiguousarray(P[:, k]) for k in range(3))
+    q = np.random.default_rng(9).uniform(-1, 1, P.shape[0])
+    ot = orc.Tree(x, y, z, 3, 0.5)
+    for l in (2, 3):
+        g, gp = ot.geom(l), ot.geom(l - 1)
+        same = sum(np.array_equal(g[i, 6:9], gp[i >> 3, 6:9]) for i in range(g.shape[0]))
+        assert same > 0, f"no child at its parent's centre on level {l}"
+        assert ot.lists(l, 1)[1].size > 0
+    gt = gpu_tree(torch, F, x, y, z, 3, 0.5)
+    assert_tree_equal(F, gt, ot, 3)
+    assert_close(gpu_eval(torch, F, gt, q, p), ot.evaluate(q, p), what=f"zero-distance translations p={p}")
+    gt.free()
+
+
 def test_nonfinite_rejected(torch, F):
     say("[edge] nonfinite")
     x, y, z, _ = W.uniform_cube(100, seed=1)
